@@ -1,0 +1,201 @@
+"""ctypes binding of the plain FP64 CPU oracle (``gals_oracle.c``).
+
+Test infrastructure only: the test suite, the smoke check and the benchmark's
+CPU-baseline leg use it; the GPU library never does. Arrays are float64 numpy
+arrays, dense and x fastest (index ``i + nx*(j + ny*k)``), with ``psi`` stored
+as ``dim`` planes back to back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gals_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libgals_oracle.so")
+
+# Velocity kinds (same numbering as the GPU library's public header; each side
+# defines its own copy).
+AFFINE, STREAM_SIN, VECPOT_SIN, VORTEX, PSEUDO1D, LEVEQUE3D = 1, 2, 3, 4, 5, 6
+MIXED_CENTRAL, MIXED_ZERO = 0, 2
+
+_lib = None
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fPIC",
+           "-shared", "-Wall", "-Wextra", "-o", _LIB_PATH, _SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    D = ctypes.POINTER(ctypes.c_double)
+    L = ctypes.POINTER(ctypes.c_long)
+    i, l, d = ctypes.c_int, ctypes.c_long, ctypes.c_double
+    lib.orc_basis.argtypes = [i, i, i, d, D]
+    lib.orc_hermite.argtypes = [i, D, D, D, D, D, D]
+    lib.orc_mixed.argtypes = [i, L, D, D, i, D, D]
+    lib.orc_velocity.argtypes = [i, i, D, l, d, D, d, D, D]
+    lib.orc_trace.argtypes = [i, i, D, l, d, D, d, d, D, D]
+    lib.orc_advance.argtypes = [i, L, D, D, i, D, l, d, i, D, D, d, d, l]
+    lib.orc_step_nodes.argtypes = [i, L, D, D, i, D, l, d, i, D, D, d, d, L, l, D, D]
+    lib.orc_eval_points.argtypes = [i, L, D, D, i, D, D, D, l, D, D, D, D, D]
+    lib.orc_norms.argtypes = [i, L, D, D, D, D, D, D, d, d, D]
+    lib.orc_max_speed.argtypes = [i, L, D, D, i, D, l, d, d]
+    lib.orc_max_speed.restype = d
+    lib.orc_num_threads.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _geom(ncell, lo, hi):
+    nc = np.ascontiguousarray(ncell, dtype=np.int64).astype(np.int_)
+    return (nc, _f64(lo), _f64(hi),
+            nc.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
+
+
+def _params(params):
+    p = _f64(params if params is not None else np.zeros(0))
+    return p, (len(p))
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} rejected its arguments")
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+def basis(v: int, alpha: int, deriv: int, x: float) -> float:
+    out = ctypes.c_double()
+    _check(_load().orc_basis(v, alpha, deriv, x, ctypes.byref(out)), "basis")
+    return out.value
+
+
+def hermite(dim, data, h, xi):
+    """Value, gradient and Hessian of the p-cubic on one cell."""
+    data, h, xi = _f64(data), _f64(h), _f64(xi)
+    val = np.zeros(1)
+    grad = np.zeros(dim)
+    hess = np.zeros(dim * dim)
+    _check(_load().orc_hermite(dim, _dp(data), _dp(h), _dp(xi), _dp(val), _dp(grad),
+                               _dp(hess)), "hermite")
+    return val[0], grad, hess.reshape(dim, dim)
+
+
+def mixed(dim, ncell, lo, hi, psi, mode=MIXED_CENTRAL):
+    nc, lo, hi, ncp = _geom(ncell, lo, hi)
+    psi = _f64(psi)
+    nodes = int(np.prod(nc + 1))
+    out = np.zeros((1 if dim == 2 else 4) * nodes)
+    _check(_load().orc_mixed(dim, ncp, _dp(lo), _dp(hi), mode, _dp(psi), _dp(out)), "mixed")
+    return out
+
+
+def velocity(dim, kind, params, period, x, t):
+    p, npar = _params(params)
+    x = _f64(x)
+    v = np.zeros(dim)
+    G = np.zeros(dim * dim)
+    _check(_load().orc_velocity(dim, kind, _dp(p), npar, period, _dp(x), t, _dp(v), _dp(G)),
+           "velocity")
+    return v, G.reshape(dim, dim)
+
+
+def trace(dim, kind, params, period, x, t, dt):
+    p, npar = _params(params)
+    x = _f64(x)
+    X = np.zeros(dim)
+    D = np.zeros(dim * dim)
+    _check(_load().orc_trace(dim, kind, _dp(p), npar, period, _dp(x), t, dt, _dp(X), _dp(D)),
+           "trace")
+    return X, D.reshape(dim, dim)
+
+
+def advance(dim, ncell, lo, hi, kind, params, period, phi, psi, t0, dt, steps,
+            mixed_mode=MIXED_CENTRAL):
+    """Return (phi, psi) after ``steps`` steps; the inputs are not modified."""
+    nc, lo, hi, ncp = _geom(ncell, lo, hi)
+    p, npar = _params(params)
+    phi = _f64(phi).copy()
+    psi = _f64(psi).copy()
+    _check(_load().orc_advance(dim, ncp, _dp(lo), _dp(hi), kind, _dp(p), npar, period,
+                               mixed_mode, _dp(phi), _dp(psi), t0, dt, int(steps)),
+           "advance")
+    return phi, psi
+
+
+def step_nodes(dim, ncell, lo, hi, kind, params, period, phi, psi, t, dt, nodes,
+               mixed_mode=MIXED_CENTRAL):
+    """One step from t to t+dt at the given flat node indices."""
+    nc, lo, hi, ncp = _geom(ncell, lo, hi)
+    p, npar = _params(params)
+    phi, psi = _f64(phi), _f64(psi)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int_)
+    cnt = len(nodes)
+    po = np.zeros(cnt)
+    go = np.zeros(cnt * dim)
+    _check(_load().orc_step_nodes(dim, ncp, _dp(lo), _dp(hi), kind, _dp(p), npar, period,
+                                  mixed_mode, _dp(phi), _dp(psi), t, dt,
+                                  nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), cnt,
+                                  _dp(po), _dp(go)), "step_nodes")
+    return po, go.reshape(cnt, dim)
+
+
+def eval_points(dim, ncell, lo, hi, phi, psi, pts, mixed_mode=MIXED_CENTRAL):
+    """pts: (npts, dim). Returns dict of val, grad, hess, normal, kappa."""
+    nc, lo, hi, ncp = _geom(ncell, lo, hi)
+    phi, psi = _f64(phi), _f64(psi)
+    pts = _f64(pts).reshape(-1, dim)
+    n = pts.shape[0]
+    val = np.zeros(n)
+    grad = np.zeros(n * dim)
+    hess = np.zeros(n * dim * dim)
+    normal = np.zeros(n * dim)
+    kappa = np.zeros(n)
+    _check(_load().orc_eval_points(dim, ncp, _dp(lo), _dp(hi), mixed_mode, _dp(phi),
+                                   _dp(psi), _dp(pts), n, _dp(val), _dp(grad), _dp(hess),
+                                   _dp(normal), _dp(kappa)), "eval_points")
+    return {"val": val, "grad": grad.reshape(n, dim), "hess": hess.reshape(n, dim, dim),
+            "normal": normal.reshape(n, dim), "kappa": kappa}
+
+
+def norms(dim, ncell, lo, hi, phi, psi, phi_ref, psi_ref, eps, band):
+    nc, lo, hi, ncp = _geom(ncell, lo, hi)
+    out = np.zeros(8)
+    args = [_f64(a) for a in (phi, psi, phi_ref, psi_ref)]
+    _check(_load().orc_norms(dim, ncp, _dp(lo), _dp(hi), *[_dp(a) for a in args], eps, band,
+                             _dp(out)), "norms")
+    return out
+
+
+def max_speed(dim, ncell, lo, hi, kind, params, period, t):
+    nc, lo, hi, ncp = _geom(ncell, lo, hi)
+    p, npar = _params(params)
+    r = _load().orc_max_speed(dim, ncp, _dp(lo), _dp(hi), kind, _dp(p), npar, period, t)
+    if r < 0:
+        raise ValueError("oracle max_speed rejected its arguments")
+    return r

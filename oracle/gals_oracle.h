@@ -1,0 +1,117 @@
+/*
+ * Plain FP64 CPU oracle for the gradient-augmented CIR (GA-CIR) level set step
+ * of Nave, Rosales and Seibold, "A gradient-augmented level set method with an
+ * optimally local, coherent advection scheme".
+ *
+ * THIS IS TEST INFRASTRUCTURE. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it. It shares no code, header, table or
+ * constant with the GPU library; the two agree only on the public argument
+ * conventions (grid geometry, velocity parameter layout), which each side
+ * implements on its own.
+ *
+ * Conventions (all arrays FP64, dense, no padding):
+ *   dim in {2,3}; ncell[a] cells along axis a; nodes per axis nn[a] = ncell[a]+1;
+ *   h[a] = (hi[a]-lo[a]) / ncell[a]; node (i,j,k) sits at lo + (i,j,k)*h.
+ *   A node field is a plane of nn[0]*nn[1]*(nn[2]) doubles, x fastest:
+ *   index = i + nn[0]*(j + nn[1]*k).
+ *   phi: 1 plane.  psi: dim planes back to back (psi_x, psi_y[, psi_z]).
+ *   Points are AoS: pts[p*dim + a].
+ *
+ * Velocity kinds and their parameter vectors (v(x,t) = c(t) * v_s(x) with
+ * c(t) = cos(pi t / period) when period > 0, else 1):
+ *   1 AFFINE     (2D/3D)  params = b[d], c[d], A[d*d] (row-major, A[i][j] = dv_i/dx_j):
+ *                          v_s = b + A (x - c)
+ *   2 STREAM_SIN (2D)     params = (a, m, n) per mode: stream function
+ *                          s = sum a sin(m pi x) sin(n pi y), v_s = (-s_y, s_x)
+ *   3 VECPOT_SIN (3D)     params = (ax, ay, az, l, m, n) per mode: vector potential
+ *                          A = sum (ax,ay,az) sin(l pi x) sin(m pi y) sin(n pi z),
+ *                          v_s = curl A
+ *   4 VORTEX     (2D)     params = none: stream function (1/pi) sin^2(pi x) sin^2(pi y)
+ *                          (the "vortex in a box" field of the accuracy study, sec. 6.1)
+ *   5 PSEUDO1D   (2D)     params = none: v_s = exp(e.x) e, e = (sqrt2, sqrtpi)/sqrt(2+pi)
+ *                          (eq. velocity_1)
+ *   6 LEVEQUE3D  (3D)     params = none: the 3D deformation field of sec. 6.2
+ *
+ * Mixed-derivative modes (sec. 2.3): 0 central differencing (A), 2 all zero.
+ */
+#ifndef GALS_ORACLE_H
+#define GALS_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* 1D basis w^v_alpha(x) of eq. (1-cubic_basis_functions) and its derivatives
+ * of order deriv in {0,1,2}. Returns 0, or -1 on bad arguments. */
+int orc_basis(int v, int alpha, int deriv, double x, double *out);
+
+/* p-cubic Hermite interpolant, eq. (p-cubic_interpolant), on one cell with
+ * edge lengths h[dim], evaluated at local coordinates xi[dim] (0..1 inside).
+ * data[v * 2^dim + alpha]: the derivative d^alpha phi at vertex v, with v and
+ * alpha bit masks (bit a = axis a). Outputs (any may be NULL):
+ * val, grad[dim], hess[dim*dim]. */
+int orc_hermite(int dim, const double *data, const double *h, const double *xi,
+                double *val, double *grad, double *hess);
+
+/* Cross derivatives at every node from psi (sec. 2.3). mode 0: central (A)
+ * with one-sided 3-point differences at the first and last node; mode 2: zero.
+ * Output planes: 2D [phi_xy]; 3D [phi_xy, phi_xz, phi_yz, phi_xyz]. */
+int orc_mixed(int dim, const long *ncell, const double *lo, const double *hi,
+              int mode, const double *psi, double *mixed);
+
+/* Velocity v(x,t) and the deformation matrix in the paper's convention
+ * G[i*dim+j] = d v_j / d x_i (sec. 4). */
+int orc_velocity(int dim, int kind, const double *params, long nparams,
+                 double period, const double *x, double t, double *v, double *G);
+
+/* Superconsistent Shu-Osher backward trace (Ex. ex:superconsistent_ShuOsher):
+ * from node position x at time t+dt back to time t. Returns the foot X[dim]
+ * and D[i*dim+j] = d X_j / d x_i. */
+int orc_trace(int dim, int kind, const double *params, long nparams, double period,
+              const double *x, double t, double dt, double *X, double *D);
+
+/* Advance phi, psi in place by `steps` GA-CIR steps of size dt from time t0.
+ * Step n goes from t0 + n dt to t0 + (n+1) dt. */
+int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
+                int kind, const double *params, long nparams, double period,
+                int mixed_mode, double *phi, double *psi,
+                double t0, double dt, long steps);
+
+/* One step from time t to t+dt, evaluated only at the listed node indices.
+ * phi_out[count], psi_out[count*dim]. */
+int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *hi,
+                   int kind, const double *params, long nparams, double period,
+                   int mixed_mode, const double *phi, const double *psi,
+                   double t, double dt, const long *nodes, long count,
+                   double *phi_out, double *psi_out);
+
+/* Value, gradient, Hessian, normal and curvature of the Hermite interpolant at
+ * npts points (sec. 3.2, eqs. surface_normal and curvature). Any output may be
+ * NULL. grad/normal: npts*dim, hess: npts*dim*dim, kappa: npts. */
+int orc_eval_points(int dim, const long *ncell, const double *lo, const double *hi,
+                    int mixed_mode, const double *phi, const double *psi,
+                    const double *pts, long npts, double *val, double *grad,
+                    double *hess, double *normal, double *kappa);
+
+/* Diagnostics over all nodes, compared with a reference state:
+ * out[0] e_max(phi), out[1] e_max(psi) (eq. maximum_norm),
+ * out[2] L1 shape error  prod(h) * sum |H_eps(phi) - H_eps(phi_ref)|,
+ * out[3] max |phi - phi_ref| over nodes with |phi_ref| <= band,
+ * out[4] volume prod(h) * sum H_eps(-phi), out[5] the same for phi_ref,
+ * out[6] number of non-finite entries in phi and psi, out[7] max |phi_ref|. */
+int orc_norms(int dim, const long *ncell, const double *lo, const double *hi,
+              const double *phi, const double *psi, const double *phi_ref,
+              const double *psi_ref, double eps, double band, double *out);
+
+/* max over nodes of |v(x_node, t)|. */
+double orc_max_speed(int dim, const long *ncell, const double *lo, const double *hi,
+                     int kind, const double *params, long nparams, double period,
+                     double t);
+
+/* Number of OpenMP threads the oracle runs with (1 without OpenMP). */
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
