@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the GA-CIR advance on one MI355X.
+
+Workload (the 2048^2 single-level-set case): 2049^2 nodes on [0,1]^2, phi =
+signed distance to the union of 4 seeded circles, velocity from an 8-mode sine
+stream function modulated by cos(pi t / 2), 1024 steps of dt = 2/1024 (CFL
+0.8); the flow reverses so the final state should return to the initial one.
+
+One benchmark step = one pass of the whole path over the workload: the full
+1024-step advance (every step: trace, split, gather, Hermite, gradient update,
+write-back) followed by the FP64 shape-error reduction against the initial
+state. The FP32-state path is timed (foot coordinates and split in FP64); the
+FP64 path runs once beside it for the matched-error comparison.
+
+Prints one JSON line. Options: --gpus (only 1 is supported), --steps K,
+--warmup W, --no-cpu (skip the oracle baseline), --inner (time steps per
+benchmark step, default the workload's 1024).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GALS node-updates/s + HBM GB/s, FP32 vs FP64 GPU at matched L1 shape error"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """Hash of the library sources; a committed traffic record applies only to
+    the kernel it was measured on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_0905_3409_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(profile_md):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
+    scaled by the counters' reading of a plain copy; None if the kernel has
+    changed since the counters were taken."""
+    import re
+    path = os.path.join(ROOT, "profiles", profile_md)
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"traffic-record: src_hash=(\w+) fetch_kib=([\d.]+) write_kib=([\d.]+) "
+                  r"fetch_scale=([\d.]+) write_scale=([\d.]+)", open(path).read())
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    kib = float(m.group(2)) * float(m.group(4)) + float(m.group(3)) * float(m.group(5))
+    return kib * 1024.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--inner", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short FP32 advance plus a plain device copy of known size "
+                         "(for calibrating rocprofv3 byte counters); prints no JSON")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design "
+              "note, not an implemented path. Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_0905_3409_amd as pkg
+    from paper_0905_3409_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    w = inputs.stream_circles()
+    inner = args.inner or w["steps"]
+    n = w["ncell"][0]
+    h = 1.0 / n
+    nodes = (n + 1) ** 2
+    eps, band = 1.5 * h, 3 * h
+    log(f"workload {w['name']} {n}^2 cells, {inner} steps/bench step, dt={w['dt']:.6g}")
+
+    def setup(dtype):
+        g = pkg.Grid(w["ncell"], w["lo"], w["hi"], dtype=dtype)
+        g.set_velocity(w["kind"], w["params"], w["period"])
+        ref = g.from_numpy(w["phi0"], w["psi0"])
+        return g, ref, ref.clone()
+
+    def bench_step(g, st, ref, ev=None):
+        if ev is not None:
+            ev[0].record()
+        g.advance(st, 0.0, w["dt"], inner)
+        if ev is not None:
+            ev[1].record()
+        return g.norms(st, ref, eps, band)  # synchronises
+
+    # ---------------------------------------------------------------- FP32
+    g32, ref32, st32 = setup("float32")
+    if args.profile:
+        steps = args.inner or 64
+        g32.advance(st32, 0.0, w["dt"], steps)
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # plain copy: reads and writes exactly 256 MiB
+        torch.cuda.synchronize()
+        log(f"profile: {steps} FP32 steps on {nodes} nodes, then a {nbytes} B device copy")
+        return 0
+    for _ in range(args.warmup):
+        bench_step(g32, st32, ref32)
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        bench_step(g32, st32, ref32, events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    adv_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    kernel_us = adv_ms * 1e3 / inner  # average step-kernel duration (launches back to back)
+    value = nodes * inner / (ms_per_step * 1e-3)
+    log(f"fp32: {ms_per_step:.2f} ms/bench step, advance {adv_ms:.2f} ms, "
+        f"step kernel {kernel_us:.2f} us, {value / 1e9:.2f} G node-upd/s")
+
+    # matched-error comparison: one fresh full run per precision
+    st32.copy_(ref32)
+    n32 = bench_step(g32, st32, ref32)
+    res = {}
+    if not args.no_fp64:
+        g64, ref64, st64 = setup("float64")
+        bench_step(g64, st64, ref64)          # warm-up
+        st64.copy_(ref64)
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        n64 = bench_step(g64, st64, ref64, ev)
+        b = time.perf_counter()
+        adv64 = ev[0].elapsed_time(ev[1])
+        res["fp64"] = {"value": nodes * inner / (b - a), "advance_ms": adv64,
+                       "step_kernel_us": adv64 * 1e3 / inner,
+                       "l1_shape_error": n64[2], "linf_band_error": n64[3],
+                       "volume_change": n64[4] - n64[5]}
+        res["l1_shape_error_ratio_fp32_over_fp64"] = n32[2] / n64[2] if n64[2] > 0 else None
+        log(f"fp64: {res['fp64']['value'] / 1e9:.2f} G node-upd/s, L1 shape err {n64[2]:.3e}; "
+            f"fp32 L1 shape err {n32[2]:.3e}")
+        del g64, ref64, st64
+    res["fp32_l1_shape_error"] = n32[2]
+    res["fp32_linf_band_error"] = n32[3]
+
+    bytes_per_node = 24  # FP32 state: 3 planes read once + 3 planes written once
+    achieved = nodes * bytes_per_node / (kernel_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS,
+                "traffic": traffic_record("k_step2d_f32_stream_2048.md"),
+                "kernel": "k_step2d<float, STREAM_SIN, CENTRAL>",
+                "bytes_per_launch": nodes * bytes_per_node, "avg_launch_us": kernel_us}
+
+    # ------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        k_cpu = 16
+        a = time.perf_counter()
+        oracle.advance(2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
+                       w["phi0"], w["psi0"], 0.0, w["dt"], k_cpu)
+        b = time.perf_counter()
+        cpu = {"value": nodes * k_cpu / (b - a), "unit": "node-updates/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"first {k_cpu} of the {w['steps']} steps of the same 2048^2 workload "
+                         f"(FP64 oracle, OpenMP), {b - a:.1f} s"}
+        log(f"cpu oracle: {cpu['value'] / 1e6:.2f} M node-upd/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "stream_circles: 2048^2 cells, 4 seeded circles, 8-mode sine "
+                               "stream function x cos(pi t/2), 1024 steps, CFL 0.8",
+                   "grid_nodes": [n + 1, n + 1], "time_steps_per_step": inner,
+                   "state": "f32", "foot_coordinates": "f64", "seed": w["seed"]},
+        "hbm_gbps_algorithmic": achieved,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        **res,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,178 @@
+/*
+ * gals.h - C ABI of the MI355X (gfx950) gradient-augmented level set library.
+ *
+ * The library advances a level set function phi and its gradient psi =
+ * grad phi, both stored on the nodes of a uniform 2D or 3D grid, with the
+ * gradient-augmented CIR scheme of Nave, Rosales and Seibold ("A
+ * gradient-augmented level set method with an optimally local, coherent
+ * advection scheme"): per node, the characteristic is traced backwards with
+ * the superconsistent Shu-Osher scheme (sec. 5.1, Ex.
+ * ex:superconsistent_ShuOsher), the bi-/tri-cubic Hermite interpolant
+ * (sec. 2.3, eq. p-cubic_interpolant) of the cell holding the foot is
+ * evaluated, and phi <- H(foot), psi <- (grad foot) . grad H(foot)
+ * (eq. superconsistency). Cross derivatives are rebuilt from neighbouring
+ * gradients by central differencing (sec. 2.3, approach (A)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid: dim in {2,3}; ncell[a] >= 2 cells on [lo[a], hi[a]]; nodes per axis
+ *   n[a] = ncell[a] + 1; h[a] = (hi[a]-lo[a]) / ncell[a]; node i sits at
+ *   lo + i*h.
+ * Device layout (SoA planes): element type float (GALS_F32) or double
+ *   (GALS_F64). A plane holds n[1] (2D) or n[1]*n[2] (3D) rows of
+ *   `pitch` elements, x fastest: element (i,j,k) at i + pitch*(j + n[1]*k).
+ *   pitch = n[0] rounded up to a multiple of 64; `plane_stride` =
+ *   pitch*n[1](*n[2]) elements. `phi` points to one plane; `grad` to dim
+ *   planes at grad + a*plane_stride (psi_x, psi_y[, psi_z]). Padding
+ *   elements are never read or written. Device pointers must be aligned to
+ *   their element size.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *   stream). Calls marked "async" only enqueue work on it.
+ * Ownership: the caller allocates and owns every device buffer (state,
+ *   workspace, points, outputs); the library owns only its context and never
+ *   frees caller memory.
+ * Errors: every entry point returns GALS_OK (0) or a negative code and never
+ *   throws; gals_last_error() returns a thread-local message describing the
+ *   last failure. Asynchronous kernel faults surface as GALS_EHIP from a
+ *   later call.
+ * Threads: a context may be used from one host thread at a time; calls that
+ *   share a workspace must be ordered on one stream.
+ */
+#ifndef GALS_H
+#define GALS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gals_ctx gals_ctx;
+
+enum { GALS_OK = 0, GALS_EINVAL = -1, GALS_ENOMEM = -2, GALS_EHIP = -3, GALS_ENOTSUP = -4 };
+
+/* State and Hermite arithmetic precision. Foot coordinates, the cell split
+ * and all reductions are FP64 in both. */
+enum { GALS_F32 = 1, GALS_F64 = 2 };
+
+/* Cross-derivative reconstruction (sec. 2.3): central differencing (A), with
+ * one-sided 3-point differences at the first and last node; or all zero (the
+ * robustness ablation noted at the end of sec. 2.3). */
+enum { GALS_MIXED_CENTRAL = 0, GALS_MIXED_ZERO = 2 };
+
+/* Treatment of a departure point (foot) outside the domain. GALS_BC_NEUMANN
+ * (the default): homogeneous Neumann, the boundary condition the paper
+ * prescribes at inflow edges in its tests (sec. 6.1, 6.2); the foot is
+ * projected onto the domain and the extension, constant along the outward
+ * normal, has zero normal derivative. GALS_BC_EXTRAPOLATE: the nearest
+ * boundary cell's polynomial is evaluated outside its cell (exact for
+ * polynomial data, but it amplifies values when feet land more than about one
+ * cell out, e.g. a rotation at CFL > 1 in the corners). */
+enum { GALS_BC_NEUMANN = 0, GALS_BC_EXTRAPOLATE = 1 };
+
+/* Velocity fields v(x,t) = c(t) v_s(x), c(t) = cos(pi t / period) when
+ * period > 0, else 1. Parameter vectors (FP64):
+ *   GALS_VEL_AFFINE     2D/3D  b[d], c[d], A[d*d] row-major, A[i][j] = dv_i/dx_j;
+ *                              v_s = b + A (x - c)  (rotation, shear, constant)
+ *   GALS_VEL_STREAM_SIN 2D     (a, m, n) per mode, 1..64 modes, m, n integers in
+ *                              1..4: stream function s = sum a sin(m pi x) sin(n pi y),
+ *                              v_s = (-s_y, s_x)
+ *   GALS_VEL_VECPOT_SIN 3D     (ax, ay, az, l, m, n) per mode, 1..8 modes, l, m, n
+ *                              integers in 1..4: A = sum (ax,ay,az) sin(l pi x)
+ *                              sin(m pi y) sin(n pi z), v_s = curl A
+ *   GALS_VEL_VORTEX     2D     none: s = sin^2(pi x) sin^2(pi y) / pi ("vortex in a
+ *                              box", sec. 6.1, eq. swirl_2d_velocity_field)
+ *   GALS_VEL_PSEUDO1D   2D     none: v_s = exp(e.x) e, e = (sqrt 2, sqrt pi)/sqrt(2+pi)
+ *                              (sec. 6.1, eq. velocity_1)
+ *   GALS_VEL_LEVEQUE3D  3D     none: the 3D deformation field of sec. 6.2, with the
+ *                              first component read as 2 sin^2(pi x) sin(2 pi y)
+ *                              sin(2 pi z) so that the field is divergence free
+ * The analytic deformation matrix of each field is used (sec. 4 assumes v and
+ * grad v exactly accessible). */
+enum {
+    GALS_VEL_AFFINE = 1,
+    GALS_VEL_STREAM_SIN = 2,
+    GALS_VEL_VECPOT_SIN = 3,
+    GALS_VEL_VORTEX = 4,
+    GALS_VEL_PSEUDO1D = 5,
+    GALS_VEL_LEVEQUE3D = 6
+};
+
+/* Create a context for one grid (the problem statement of sec. 2.1: a
+ * surface moved by a given velocity, phi and psi on grid nodes). `device` is
+ * the HIP device the context launches on; -1 makes a host-only context that
+ * answers layout, workspace and parameter-validation calls and rejects every
+ * device call with EINVAL (no HIP call is made). EINVAL on dim not in {2,3},
+ * ncell[a] < 2, hi <= lo, non-finite bounds, unknown prec, mixed_mode or bc, a
+ * device outside [-1, device count), or 2^31 or more nodes; EHIP if the
+ * device count cannot be read. */
+int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo,
+                const double *hi, int prec, int mixed_mode, int bc, int device);
+
+/* Release a context (NULL is accepted). */
+int gals_destroy(gals_ctx *ctx);
+
+/* Report the device layout: nodes[dim] per axis, row pitch and plane stride
+ * in elements. Any output may be NULL. */
+int gals_layout(const gals_ctx *ctx, int64_t *nodes, int64_t *pitch,
+                int64_t *plane_stride);
+
+/* Workspace bytes every call on this context needs (one ping-pong copy of
+ * the state plus reduction partials), aligned to 256 bytes. */
+int gals_workspace_bytes(const gals_ctx *ctx, size_t *bytes);
+
+/* Set the velocity field (sec. 4). EINVAL on a wrong parameter count, kind
+ * not valid for the grid's dim, non-finite parameters or period < 0;
+ * ENOTSUP on sine-mode indices outside 1..4 or too many modes. Host-only. */
+int gals_set_velocity(gals_ctx *ctx, int kind, const double *params, int64_t nparams,
+                      double period);
+
+/* Advance phi and grad (device, in place) by `steps` GA-CIR steps of size dt
+ * from time t0 (sec. 4, steps 1-3, with the superconsistent update of eq.
+ * superconsistency). Step n goes from t0 + n*dt to t0 + (n+1)*dt; times are
+ * computed, not accumulated. Departure points may lie any number of cells
+ * away (any CFL); feet outside the domain follow the context's boundary
+ * treatment. Async. EINVAL on NULL or overlapping state/workspace
+ * pointers, workspace smaller than gals_workspace_bytes, non-finite or
+ * non-positive dt, non-finite t0, steps < 0, or no velocity set. */
+int gals_advance(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int64_t steps,
+                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* Value, unit normal and curvature of the Hermite interpolant at npts points
+ * (sec. 3.2, eqs. surface_normal and curvature; in 3D the curvature is the
+ * divergence of the normal, i.e. the sum of the principal curvatures).
+ * pts: device FP64, SoA (x[npts], y[npts][, z[npts]]). Outputs are device
+ * arrays of the context's element type: val[npts], normal[dim*npts] (SoA),
+ * curv[npts]; any output may be NULL. Where the gradient is exactly zero the
+ * normal and curvature are 0. A point outside the domain evaluates the
+ * nearest boundary cell's polynomial. Async. EINVAL on NULL state/points or
+ * npts < 0. */
+int gals_eval_points(gals_ctx *ctx, const void *phi, const void *grad, const double *pts,
+                     int64_t npts, void *val, void *normal, void *curv, void *stream);
+
+/* max over nodes of |v(x_node, t)| into *out (host). Uses the workspace for
+ * partials, synchronises the stream. */
+int gals_max_speed(gals_ctx *ctx, double t, double *out, void *workspace,
+                   size_t workspace_bytes, void *stream);
+
+/* Error norms of (phi, grad) against a reference state (sec. 6.1, eq.
+ * maximum_norm), FP64 accumulation, deterministic. out[8] (host):
+ *   [0] max |phi - phi_ref|              [1] max over components |psi - psi_ref|
+ *   [2] prod(h) * sum |H_eps(phi) - H_eps(phi_ref)|  (L1 shape error)
+ *   [3] max |phi - phi_ref| over nodes with |phi_ref| <= band
+ *   [4] prod(h) * sum H_eps(-phi)        [5] the same for phi_ref (volumes)
+ *   [6] count of non-finite entries of phi and grad   [7] max |phi_ref|
+ * with H_eps(s) = 0 (s < -eps), 1 (s > eps), (1 + s/eps + sin(pi s/eps)/pi)/2.
+ * Uses the workspace for partials, synchronises the stream. */
+int gals_norms(gals_ctx *ctx, const void *phi, const void *grad, const void *phi_ref,
+               const void *grad_ref, double eps, double band, double *out,
+               void *workspace, size_t workspace_bytes, void *stream);
+
+/* Thread-local text of the last error ("" if none). */
+const char *gals_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GALS_H */

@@ -20,8 +20,12 @@
  *   - cross derivatives at the first/last node use one-sided 3-point
  *     differences; phi_xy = D_x psi_y, phi_xz = D_x psi_z, phi_yz = D_y psi_z,
  *     phi_xyz = D_x D_y psi_z (the highest-index gradient component);
- *   - a foot outside the domain uses the nearest boundary cell's polynomial
- *     (clamped cell index, unclamped local coordinate);
+ *   - a foot outside the domain: with bc = 0 (homogeneous Neumann, as the
+ *     paper prescribes at inflow edges in its tests, sec. 6.1 and 6.2) the
+ *     foot is projected onto the domain and the extension, constant along
+ *     the outward normal, has zero normal derivative; with bc = 1 the
+ *     nearest boundary cell's polynomial is extrapolated (clamped cell index,
+ *     unclamped local coordinate). Point evaluation always extrapolates;
  *   - a foot exactly on a cell face belongs to the cell on its right,
  *     except at the last node, which belongs to the last cell (xi = 1);
  *   - 3D curvature is the divergence of the unit normal (sum of the principal
@@ -503,19 +507,30 @@ static void gather_cell(const grid_t *g, const long *cell, const double *phi,
 /* One GA-CIR step at node idx (sec. 4, steps 1-3, with the superconsistent
  * gradient update of eq. superconsistency). */
 static int step_node(const grid_t *g, int kind, const double *params, long np,
-                     double period, const double *phi, const double *psi,
+                     double period, int bc, const double *phi, const double *psi,
                      const double *mixed, double t, double dt, long idx,
                      double *phi_new, double *psi_new)
 {
     int d = g->dim;
     long ijk[MAXD], cell[MAXD];
     double x[MAXD], X[MAXD], D[9], xi[MAXD], data[64], val, grad[MAXD];
+    int outside[MAXD] = {0, 0, 0};
     node_coords(g, idx, ijk);
     for (int a = 0; a < d; a++) x[a] = g->lo[a] + (double)ijk[a] * g->h[a];
     if (orc_trace(d, kind, params, np, period, x, t, dt, X, D)) return -1;
+    if (bc == 0) {
+        /* homogeneous Neumann: project the foot onto the domain */
+        for (int a = 0; a < d; a++) {
+            double top = g->lo[a] + (double)g->nc[a] * g->h[a];
+            if (X[a] < g->lo[a]) { X[a] = g->lo[a]; outside[a] = 1; }
+            else if (X[a] > top) { X[a] = top; outside[a] = 1; }
+        }
+    }
     locate(g, X, cell, xi);
     gather_cell(g, cell, phi, psi, mixed, data);
     orc_hermite(d, data, g->h, xi, &val, grad, NULL);
+    for (int a = 0; a < d; a++)
+        if (outside[a]) grad[a] = 0.0; /* the extension is constant along the normal */
     *phi_new = val;
     for (int i = 0; i < d; i++) {
         double s = 0.0;
@@ -527,11 +542,12 @@ static int step_node(const grid_t *g, int kind, const double *params, long np,
 
 int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
                 int kind, const double *params, long nparams, double period,
-                int mixed_mode, double *phi, double *psi,
+                int mixed_mode, int bc, double *phi, double *psi,
                 double t0, double dt, long steps)
 {
     grid_t g;
-    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || steps < 0) return -1;
+    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || steps < 0 || bc < 0 || bc > 1)
+        return -1;
     long N = g.nodes;
     int nm = (dim == 2) ? 1 : 4;
     double *mixed = (double *)malloc(sizeof(double) * (size_t)(nm * N));
@@ -545,7 +561,7 @@ int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
 #pragma omp parallel for schedule(static) reduction(| : bad)
         for (long idx = 0; idx < N; idx++) {
             double pn, gn[MAXD];
-            if (step_node(&g, kind, params, nparams, period, phi, psi, mixed, t, dt,
+            if (step_node(&g, kind, params, nparams, period, bc, phi, psi, mixed, t, dt,
                           idx, &pn, gn)) {
                 bad = 1;
                 continue;
@@ -563,12 +579,13 @@ int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
 
 int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *hi,
                    int kind, const double *params, long nparams, double period,
-                   int mixed_mode, const double *phi, const double *psi,
+                   int mixed_mode, int bc, const double *phi, const double *psi,
                    double t, double dt, const long *nodes, long count,
                    double *phi_out, double *psi_out)
 {
     grid_t g;
-    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || !nodes || count < 0)
+    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || !nodes || count < 0 ||
+        bc < 0 || bc > 1)
         return -1;
     long N = g.nodes;
     int nm = (dim == 2) ? 1 : 4;
@@ -577,7 +594,7 @@ int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *h
     int err = mixed_planes(&g, mixed_mode, psi, mixed);
     for (long k = 0; k < count && !err; k++) {
         if (nodes[k] < 0 || nodes[k] >= N) { err = -1; break; }
-        err = step_node(&g, kind, params, nparams, period, phi, psi, mixed, t, dt,
+        err = step_node(&g, kind, params, nparams, period, bc, phi, psi, mixed, t, dt,
                         nodes[k], &phi_out[k], &psi_out[k * dim]);
     }
     free(mixed);

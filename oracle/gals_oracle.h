@@ -33,6 +33,9 @@
  *   6 LEVEQUE3D  (3D)     params = none: the 3D deformation field of sec. 6.2
  *
  * Mixed-derivative modes (sec. 2.3): 0 central differencing (A), 2 all zero.
+ * Boundary treatment of feet outside the domain (bc): 0 homogeneous Neumann
+ * (foot projected onto the domain, zero normal derivative), 1 extrapolation
+ * of the boundary cell's polynomial.
  */
 #ifndef GALS_ORACLE_H
 #define GALS_ORACLE_H
@@ -74,14 +77,14 @@ int orc_trace(int dim, int kind, const double *params, long nparams, double peri
  * Step n goes from t0 + n dt to t0 + (n+1) dt. */
 int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
                 int kind, const double *params, long nparams, double period,
-                int mixed_mode, double *phi, double *psi,
+                int mixed_mode, int bc, double *phi, double *psi,
                 double t0, double dt, long steps);
 
 /* One step from time t to t+dt, evaluated only at the listed node indices.
  * phi_out[count], psi_out[count*dim]. */
 int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *hi,
                    int kind, const double *params, long nparams, double period,
-                   int mixed_mode, const double *phi, const double *psi,
+                   int mixed_mode, int bc, const double *phi, const double *psi,
                    double t, double dt, const long *nodes, long count,
                    double *phi_out, double *psi_out);
 

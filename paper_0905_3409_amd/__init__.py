@@ -1,0 +1,240 @@
+"""MI355X (gfx950) gradient-augmented level set advection.
+
+A thin ctypes binding over ``libgals.so`` (C ABI in ``include/gals.h``).
+PyTorch only supplies device memory and the stream; every step of the method
+runs in the library's HIP kernels. There is no CPU fallback: if the library is
+not built, every call raises.
+
+Typical use::
+
+    g = Grid((2048, 2048), dtype="float32")
+    g.set_velocity(STREAM_SIN, params, period=2.0)
+    state = g.from_numpy(phi0, psi0)        # (1+dim, plane) device tensor
+    g.advance(state, t0=0.0, dt=2/1024, steps=1024)
+    phi, psi = g.to_numpy(state)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgals.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSUP = 0, -1, -2, -3, -4
+F32, F64 = 1, 2
+MIXED_CENTRAL, MIXED_ZERO = 0, 2
+BC_NEUMANN, BC_EXTRAPOLATE = 0, 1
+AFFINE, STREAM_SIN, VECPOT_SIN, VORTEX, PSEUDO1D, LEVEQUE3D = 1, 2, 3, 4, 5, 6
+
+EXPORTS = ("gals_create", "gals_destroy", "gals_layout", "gals_workspace_bytes",
+           "gals_set_velocity", "gals_advance", "gals_eval_points", "gals_max_speed",
+           "gals_norms", "gals_last_error")
+
+_lib = None
+
+
+class GalsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def lib():
+    """Load libgals.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_0905_3409_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, i64, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    PD = ctypes.POINTER(ctypes.c_double)
+    L.gals_create.argtypes = [ctypes.POINTER(vp), i, P64, PD, PD, i, i, i, i]
+    L.gals_destroy.argtypes = [vp]
+    L.gals_layout.argtypes = [vp, P64, P64, P64]
+    L.gals_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.gals_set_velocity.argtypes = [vp, i, PD, i64, d]
+    L.gals_advance.argtypes = [vp, vp, vp, d, d, i64, vp, sz, vp]
+    L.gals_eval_points.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp]
+    L.gals_max_speed.argtypes = [vp, d, PD, vp, sz, vp]
+    L.gals_norms.argtypes = [vp, vp, vp, vp, vp, d, d, PD, vp, sz, vp]
+    L.gals_last_error.argtypes = []
+    L.gals_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "gals_last_error":
+            getattr(L, name).restype = i
+    _lib = L
+    return L
+
+
+def check(rc):
+    if rc != OK:
+        raise GalsError(rc, lib().gals_last_error().decode())
+    return rc
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Grid:
+    """A uniform 2D/3D grid with its device layout and velocity field."""
+
+    def __init__(self, ncell, lo=None, hi=None, dtype="float32", mixed=MIXED_CENTRAL,
+                 bc=BC_NEUMANN, device=0):
+        self.dim = len(ncell)
+        self.ncell = tuple(int(n) for n in ncell)
+        self.lo = tuple(float(x) for x in (lo if lo is not None else (0.0,) * self.dim))
+        self.hi = tuple(float(x) for x in (hi if hi is not None else (1.0,) * self.dim))
+        if dtype in ("float32", "f32", np.float32):
+            self.prec, self.np_dtype = F32, np.float32
+        elif dtype in ("float64", "f64", np.float64):
+            self.prec, self.np_dtype = F64, np.float64
+        else:
+            raise ValueError(f"unsupported dtype {dtype!r}")
+        self.device = int(device)
+        self._ctx = ctypes.c_void_p()
+        nc = (ctypes.c_int64 * self.dim)(*self.ncell)
+        lo_ = (ctypes.c_double * self.dim)(*self.lo)
+        hi_ = (ctypes.c_double * self.dim)(*self.hi)
+        check(lib().gals_create(ctypes.byref(self._ctx), self.dim, nc, lo_, hi_, self.prec,
+                                int(mixed), int(bc), self.device))
+        nodes = (ctypes.c_int64 * self.dim)()
+        pitch, plane = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().gals_layout(self._ctx, nodes, ctypes.byref(pitch), ctypes.byref(plane)))
+        self.nodes = tuple(nodes)
+        self.pitch = pitch.value
+        self.plane = plane.value
+        wsb = ctypes.c_size_t()
+        check(lib().gals_workspace_bytes(self._ctx, ctypes.byref(wsb)))
+        self.workspace_bytes = wsb.value
+        self._ws = None
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value and _lib is not None:
+            _lib.gals_destroy(ctx)
+            self._ctx = None
+
+    # ---------------------------------------------------------------- layout
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float32 if self.prec == F32 else torch.float64
+
+    @property
+    def num_nodes(self):
+        return int(np.prod(self.nodes))
+
+    def _dev(self):
+        import torch
+        return torch.device("cuda", self.device)
+
+    def empty_state(self):
+        """Zero-filled (1+dim, plane) device tensor: row 0 is phi, rows 1..dim psi."""
+        import torch
+        return torch.zeros((1 + self.dim, self.plane), dtype=self.torch_dtype, device=self._dev())
+
+    def _grid_view(self, plane_tensor):
+        """Dense view (z, y, x) or (y, x) of one padded plane."""
+        shape = tuple(reversed(self.nodes[1:])) + (self.pitch,)
+        v = plane_tensor.view(*shape)
+        return v[..., : self.nodes[0]]
+
+    def from_numpy(self, phi, psi):
+        """Device state from dense float64 arrays (x fastest; psi = dim planes)."""
+        import torch
+        st = self.empty_state()
+        shape = tuple(reversed(self.nodes))
+        phi = np.asarray(phi).reshape(shape)
+        psi = np.asarray(psi).reshape((self.dim,) + shape)
+        self._grid_view(st[0]).copy_(torch.from_numpy(np.ascontiguousarray(phi)).to(st.dtype))
+        for a in range(self.dim):
+            self._grid_view(st[1 + a]).copy_(
+                torch.from_numpy(np.ascontiguousarray(psi[a])).to(st.dtype))
+        return st
+
+    def to_numpy(self, state):
+        """Dense float64 (phi, psi) arrays from a device state."""
+        phi = self._grid_view(state[0]).double().cpu().numpy().ravel()
+        psi = np.concatenate([self._grid_view(state[1 + a]).double().cpu().numpy().ravel()
+                              for a in range(self.dim)])
+        return phi, psi
+
+    def workspace(self):
+        import torch
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self._dev())
+        return self._ws
+
+    def _check_state(self, state):
+        if (state.dtype != self.torch_dtype or tuple(state.shape) != (1 + self.dim, self.plane)
+                or not state.is_contiguous() or state.device != self._dev()):
+            raise ValueError("state must be a contiguous (1+dim, plane) tensor of the grid's "
+                             "dtype on the grid's device")
+
+    # ------------------------------------------------------------------- calls
+    def set_velocity(self, kind, params=(), period=0.0):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        ptr = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if p.size else None
+        check(lib().gals_set_velocity(self._ctx, int(kind), ptr, p.size, float(period)))
+
+    def advance(self, state, t0, dt, steps, stream=None):
+        """Advance the state in place (asynchronous on the stream)."""
+        self._check_state(state)
+        ws = self.workspace()
+        check(lib().gals_advance(self._ctx, ctypes.c_void_p(state[0].data_ptr()),
+                                 ctypes.c_void_p(state[1].data_ptr()), float(t0), float(dt),
+                                 int(steps), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                 _stream_handle(stream, self._dev())))
+        return state
+
+    def eval_points(self, state, pts, stream=None):
+        """Value, unit normal (dim, npts) and curvature at points (npts, dim)."""
+        import torch
+        self._check_state(state)
+        pts = torch.as_tensor(pts, dtype=torch.float64, device=self._dev())
+        n = pts.shape[0]
+        soa = pts.t().contiguous()
+        val = torch.empty(n, dtype=self.torch_dtype, device=self._dev())
+        nrm = torch.empty((self.dim, n), dtype=self.torch_dtype, device=self._dev())
+        cur = torch.empty(n, dtype=self.torch_dtype, device=self._dev())
+        check(lib().gals_eval_points(self._ctx, ctypes.c_void_p(state[0].data_ptr()),
+                                     ctypes.c_void_p(state[1].data_ptr()),
+                                     ctypes.c_void_p(soa.data_ptr()), n,
+                                     ctypes.c_void_p(val.data_ptr()),
+                                     ctypes.c_void_p(nrm.data_ptr()),
+                                     ctypes.c_void_p(cur.data_ptr()),
+                                     _stream_handle(stream, self._dev())))
+        # keep the SoA copy alive until the kernel has consumed it
+        (stream or torch.cuda.current_stream(self._dev())).synchronize()
+        return val, nrm, cur
+
+    def max_speed(self, t, stream=None):
+        out = ctypes.c_double()
+        ws = self.workspace()
+        check(lib().gals_max_speed(self._ctx, float(t), ctypes.byref(out),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream_handle(stream, self._dev())))
+        return out.value
+
+    def norms(self, state, ref, eps, band, stream=None):
+        """8 diagnostics of state against ref (see gals_norms)."""
+        self._check_state(state)
+        self._check_state(ref)
+        out = (ctypes.c_double * 8)()
+        ws = self.workspace()
+        check(lib().gals_norms(self._ctx, ctypes.c_void_p(state[0].data_ptr()),
+                               ctypes.c_void_p(state[1].data_ptr()),
+                               ctypes.c_void_p(ref[0].data_ptr()),
+                               ctypes.c_void_p(ref[1].data_ptr()), float(eps), float(band), out,
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                               _stream_handle(stream, self._dev())))
+        return np.array(out[:])

@@ -1,0 +1,399 @@
+// Host runtime of the C ABI declared in include/gals.h: argument validation,
+// velocity-parameter preparation, workspace layout and launch sequencing.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "gals_internal.h"
+
+using namespace gals;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(GALS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t elem_size(const gals_ctx *c) { return c->prec == GALS_F32 ? 4 : 8; }
+
+size_t state_bytes(const gals_ctx *c)
+{
+    return size_t(1 + c->dim) * size_t(c->g.plane) * elem_size(c);
+}
+
+size_t partial_offset(const gals_ctx *c) { return align256(state_bytes(c)); }
+
+size_t workspace_bytes(const gals_ctx *c)
+{
+    return partial_offset(c) + align256(sizeof(double) * size_t(kRedBlocks + 1) * kRedSlots);
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+bool aligned(const void *p, size_t a) { return (uintptr_t(p) % a) == 0; }
+
+// Make the context's device current for the duration of a call.
+struct DeviceGuard {
+    int old = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&old) != hipSuccess) old = -1;
+        if (old != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+    }
+};
+
+double time_factor(double period, double t) { return period > 0.0 ? cos(M_PI * t / period) : 1.0; }
+
+template <typename T>
+void fill_vel(Vel<T> &v, int kind, int dim, const double *p, int64_t np)
+{
+    memset(&v, 0, sizeof(v));
+    v.kind = kind;
+    if (kind == GALS_VEL_AFFINE) {
+        for (int i = 0; i < dim; i++) {
+            v.b[i] = T(p[i]);
+            v.c[i] = p[dim + i];
+            for (int j = 0; j < dim; j++) v.A[i * 3 + j] = T(p[2 * dim + i * dim + j]);
+        }
+    } else if (kind == GALS_VEL_STREAM_SIN) {
+        double S[4][4] = {{0}};
+        for (int64_t k = 0; k < np / 3; k++) {
+            const int m = int(p[3 * k + 1]), n = int(p[3 * k + 2]);
+            S[m - 1][n - 1] += p[3 * k];
+        }
+        for (int m = 0; m < 4; m++)
+            for (int n = 0; n < 4; n++) {
+                const double kn = (n + 1) * M_PI;
+                v.S[m][n] = T(S[m][n]);
+                v.SQ[m][n] = T(S[m][n] * kn);
+                v.SR[m][n] = T(S[m][n] * kn * kn);
+            }
+    } else if (kind == GALS_VEL_VECPOT_SIN) {
+        v.nvp = int(np / 6);
+        for (int k = 0; k < v.nvp; k++) {
+            const double *q = p + 6 * k;
+            const double ax = q[0], ay = q[1], az = q[2];
+            const double L = q[3] * M_PI, M = q[4] * M_PI, N = q[5] * M_PI;
+            for (int a = 0; a < 3; a++) v.vpi[k][a] = int(q[3 + a]);
+            const double c[21] = {az * M, ay * N, ax * N, az * L, ay * L, ax * M,
+                                  az * L * M, ay * L * N, az * M * M, ay * M * N, az * M * N,
+                                  ay * N * N, ax * L * N, az * L * L, ax * M * N, ax * N * N,
+                                  az * L * N, ay * L * L, ax * L * M, ay * L * M, ax * M * M};
+            for (int i = 0; i < 21; i++) v.vpc[k][i] = T(c[i]);
+        }
+    }
+}
+
+bool is_int_in(double x, int lo, int hi) { return x == floor(x) && x >= lo && x <= hi; }
+
+}  // namespace
+
+extern "C" {
+
+const char *gals_last_error(void) { return g_err; }
+
+int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo, const double *hi,
+                int prec, int mixed_mode, int bc, int device)
+{
+    if (!out) return fail(GALS_EINVAL, "gals_create: out is NULL");
+    *out = nullptr;
+    if (dim != 2 && dim != 3) return fail(GALS_EINVAL, "gals_create: dim must be 2 or 3 (got %d)", dim);
+    if (!ncell || !lo || !hi) return fail(GALS_EINVAL, "gals_create: NULL ncell/lo/hi");
+    if (prec != GALS_F32 && prec != GALS_F64)
+        return fail(GALS_EINVAL, "gals_create: unknown precision %d", prec);
+    if (mixed_mode != GALS_MIXED_CENTRAL && mixed_mode != GALS_MIXED_ZERO)
+        return fail(GALS_EINVAL, "gals_create: unknown mixed-derivative mode %d", mixed_mode);
+    if (bc != GALS_BC_NEUMANN && bc != GALS_BC_EXTRAPOLATE)
+        return fail(GALS_EINVAL, "gals_create: unknown boundary treatment %d", bc);
+    Geom g;
+    memset(&g, 0, sizeof(g));
+    g.dim = dim;
+    g.bc = bc;
+    int64_t nodes = 1;
+    for (int a = 0; a < 3; a++) {
+        g.n[a] = 1;
+        g.h[a] = g.inv_h[a] = 1.0;
+    }
+    for (int a = 0; a < dim; a++) {
+        if (ncell[a] < 2 || ncell[a] > (int64_t(1) << 30))
+            return fail(GALS_EINVAL, "gals_create: ncell[%d] = %lld out of range [2, 2^30]", a,
+                        (long long)ncell[a]);
+        if (!isfinite(lo[a]) || !isfinite(hi[a]) || !(hi[a] > lo[a]))
+            return fail(GALS_EINVAL, "gals_create: bounds of axis %d must be finite with hi > lo", a);
+        g.nc[a] = int(ncell[a]);
+        g.n[a] = int(ncell[a] + 1);
+        g.lo[a] = lo[a];
+        g.h[a] = (hi[a] - lo[a]) / double(ncell[a]);
+        g.inv_h[a] = 1.0 / g.h[a];
+        g.top[a] = g.lo[a] + double(g.nc[a]) * g.h[a];
+        nodes *= g.n[a];
+        if (nodes >= (int64_t(1) << 31))
+            return fail(GALS_EINVAL, "gals_create: more than 2^31 - 1 nodes");
+    }
+    g.nodes = nodes;
+    g.pitch = (int64_t(g.n[0]) + 63) / 64 * 64;
+    g.plane = g.pitch * g.n[1] * g.n[2];
+    if (g.plane > (int64_t(1) << 40)) return fail(GALS_EINVAL, "gals_create: plane too large");
+    if (device != -1) {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess) return hip_fail(e, "gals_create: hipGetDeviceCount");
+        if (device < 0 || device >= count)
+            return fail(GALS_EINVAL, "gals_create: device %d not in [0, %d)", device, count);
+    }
+    gals_ctx *c = new (std::nothrow) gals_ctx;
+    if (!c) return fail(GALS_ENOMEM, "gals_create: out of host memory");
+    memset(c, 0, sizeof(*c));
+    c->dim = dim;
+    c->prec = prec;
+    c->mixed = mixed_mode;
+    c->device = device;
+    c->g = g;
+    c->vel_set = false;
+    *out = c;
+    return GALS_OK;
+}
+
+int gals_destroy(gals_ctx *ctx)
+{
+    delete ctx;
+    return GALS_OK;
+}
+
+int gals_layout(const gals_ctx *ctx, int64_t *nodes, int64_t *pitch, int64_t *plane_stride)
+{
+    if (!ctx) return fail(GALS_EINVAL, "gals_layout: NULL context");
+    if (nodes)
+        for (int a = 0; a < ctx->dim; a++) nodes[a] = ctx->g.n[a];
+    if (pitch) *pitch = ctx->g.pitch;
+    if (plane_stride) *plane_stride = ctx->g.plane;
+    return GALS_OK;
+}
+
+int gals_workspace_bytes(const gals_ctx *ctx, size_t *bytes)
+{
+    if (!ctx || !bytes) return fail(GALS_EINVAL, "gals_workspace_bytes: NULL argument");
+    *bytes = workspace_bytes(ctx);
+    return GALS_OK;
+}
+
+int gals_set_velocity(gals_ctx *ctx, int kind, const double *params, int64_t nparams,
+                      double period)
+{
+    if (!ctx) return fail(GALS_EINVAL, "gals_set_velocity: NULL context");
+    if (nparams < 0 || (nparams > 0 && !params))
+        return fail(GALS_EINVAL, "gals_set_velocity: bad parameter vector");
+    if (!isfinite(period) || period < 0.0)
+        return fail(GALS_EINVAL, "gals_set_velocity: period must be finite and >= 0");
+    for (int64_t k = 0; k < nparams; k++)
+        if (!isfinite(params[k])) return fail(GALS_EINVAL, "gals_set_velocity: non-finite parameter");
+    const int d = ctx->dim;
+    switch (kind) {
+    case GALS_VEL_AFFINE:
+        if (nparams != 2 * d + d * d)
+            return fail(GALS_EINVAL, "gals_set_velocity: AFFINE needs %d parameters", 2 * d + d * d);
+        break;
+    case GALS_VEL_STREAM_SIN:
+        if (d != 2) return fail(GALS_EINVAL, "gals_set_velocity: STREAM_SIN is 2D");
+        if (nparams == 0 || nparams % 3)
+            return fail(GALS_EINVAL, "gals_set_velocity: STREAM_SIN needs 3 parameters per mode");
+        if (nparams / 3 > kMaxStreamModes)
+            return fail(GALS_ENOTSUP, "gals_set_velocity: at most %d stream modes", kMaxStreamModes);
+        for (int64_t k = 0; k < nparams / 3; k++)
+            if (!is_int_in(params[3 * k + 1], 1, 4) || !is_int_in(params[3 * k + 2], 1, 4))
+                return fail(GALS_ENOTSUP, "gals_set_velocity: wavenumbers must be integers in 1..4");
+        break;
+    case GALS_VEL_VECPOT_SIN:
+        if (d != 3) return fail(GALS_EINVAL, "gals_set_velocity: VECPOT_SIN is 3D");
+        if (nparams == 0 || nparams % 6)
+            return fail(GALS_EINVAL, "gals_set_velocity: VECPOT_SIN needs 6 parameters per mode");
+        if (nparams / 6 > kMaxVecpotModes)
+            return fail(GALS_ENOTSUP, "gals_set_velocity: at most %d vector-potential modes",
+                        kMaxVecpotModes);
+        for (int64_t k = 0; k < nparams / 6; k++)
+            for (int a = 3; a < 6; a++)
+                if (!is_int_in(params[6 * k + a], 1, 4))
+                    return fail(GALS_ENOTSUP, "gals_set_velocity: wavenumbers must be integers in 1..4");
+        break;
+    case GALS_VEL_VORTEX:
+    case GALS_VEL_PSEUDO1D:
+        if (d != 2) return fail(GALS_EINVAL, "gals_set_velocity: field %d is 2D", kind);
+        if (nparams != 0) return fail(GALS_EINVAL, "gals_set_velocity: field %d takes no parameters", kind);
+        break;
+    case GALS_VEL_LEVEQUE3D:
+        if (d != 3) return fail(GALS_EINVAL, "gals_set_velocity: LEVEQUE3D is 3D");
+        if (nparams != 0) return fail(GALS_EINVAL, "gals_set_velocity: LEVEQUE3D takes no parameters");
+        break;
+    default:
+        return fail(GALS_EINVAL, "gals_set_velocity: unknown velocity kind %d", kind);
+    }
+    ctx->vel_kind = kind;
+    ctx->period = period;
+    fill_vel(ctx->vf, kind, d, params, nparams);
+    fill_vel(ctx->vd, kind, d, params, nparams);
+    ctx->vel_set = true;
+    return GALS_OK;
+}
+
+int gals_advance(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int64_t steps,
+                 void *workspace, size_t workspace_bytes_, void *stream)
+{
+    if (!ctx) return fail(GALS_EINVAL, "gals_advance: NULL context");
+    if (!phi || !grad || !workspace) return fail(GALS_EINVAL, "gals_advance: NULL pointer");
+    if (!ctx->vel_set) return fail(GALS_EINVAL, "gals_advance: no velocity set");
+    if (!isfinite(dt) || !(dt > 0.0)) return fail(GALS_EINVAL, "gals_advance: dt must be finite and > 0");
+    if (!isfinite(t0)) return fail(GALS_EINVAL, "gals_advance: t0 must be finite");
+    if (steps < 0) return fail(GALS_EINVAL, "gals_advance: steps < 0");
+    const size_t es = elem_size(ctx);
+    if (!aligned(phi, es) || !aligned(grad, es) || !aligned(workspace, 256))
+        return fail(GALS_EINVAL, "gals_advance: misaligned pointer");
+    if (workspace_bytes_ < workspace_bytes(ctx))
+        return fail(GALS_EINVAL, "gals_advance: workspace of %zu bytes, %zu needed", workspace_bytes_,
+                    workspace_bytes(ctx));
+    const size_t pb = size_t(ctx->g.plane) * es;
+    const size_t gb = pb * size_t(ctx->dim);
+    if (overlap(phi, pb, grad, gb) || overlap(phi, pb, workspace, workspace_bytes_) ||
+        overlap(grad, gb, workspace, workspace_bytes_))
+        return fail(GALS_EINVAL, "gals_advance: phi, grad and workspace must not overlap");
+    if (steps == 0) return GALS_OK;
+    if (ctx->device < 0) return fail(GALS_EINVAL, "gals_advance: host-only context (device -1)");
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "gals_advance: hipSetDevice");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gals_advance: pending HIP error");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    void *bufs[2][2] = {{phi, grad}, {ws, ws + pb}};
+    for (int64_t n = 0; n < steps; n++) {
+        const double t = t0 + double(n) * dt;
+        const double c1 = time_factor(ctx->period, t + dt);
+        const double c2 = time_factor(ctx->period, t);
+        const double c3 = time_factor(ctx->period, t + 0.5 * dt);
+        void **src = bufs[n & 1], **dst = bufs[(n + 1) & 1];
+        e = launch_step(ctx, src[0], src[1], dst[0], dst[1], dt, c1, c2, c3, s);
+        if (e != hipSuccess) return hip_fail(e, "gals_advance: step launch");
+    }
+    if (steps & 1) {
+        // the result sits in the workspace: copy the valid part of each plane back
+        const size_t w = size_t(ctx->g.n[0]) * es, p = size_t(ctx->g.pitch) * es;
+        const size_t rows = size_t(ctx->g.n[1]) * size_t(ctx->g.n[2]);
+        for (int a = 0; a <= ctx->dim; a++) {
+            char *dstp = a == 0 ? (char *)phi : (char *)grad + size_t(a - 1) * pb;
+            e = hipMemcpy2DAsync(dstp, p, ws + size_t(a) * pb, p, w, rows, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "gals_advance: copy back");
+        }
+    }
+    return GALS_OK;
+}
+
+int gals_eval_points(gals_ctx *ctx, const void *phi, const void *grad, const double *pts,
+                     int64_t npts, void *val, void *normal, void *curv, void *stream)
+{
+    if (!ctx) return fail(GALS_EINVAL, "gals_eval_points: NULL context");
+    if (npts < 0) return fail(GALS_EINVAL, "gals_eval_points: npts < 0");
+    if (npts == 0) return GALS_OK;
+    if (!phi || !grad || !pts) return fail(GALS_EINVAL, "gals_eval_points: NULL pointer");
+    if (npts >= (int64_t(1) << 40)) return fail(GALS_EINVAL, "gals_eval_points: too many points");
+    const size_t es = elem_size(ctx);
+    if (!aligned(phi, es) || !aligned(grad, es) || !aligned(pts, 8) || !aligned(val, es) ||
+        !aligned(normal, es) || !aligned(curv, es))
+        return fail(GALS_EINVAL, "gals_eval_points: misaligned pointer");
+    if (ctx->device < 0) return fail(GALS_EINVAL, "gals_eval_points: host-only context (device -1)");
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "gals_eval_points: hipSetDevice");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gals_eval_points: pending HIP error");
+    e = launch_eval(ctx, phi, grad, pts, npts, val, normal, curv, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gals_eval_points: launch");
+    return GALS_OK;
+}
+
+static int finish_reduction(const gals_ctx *ctx, const double *dev_out, double *host_out, int n,
+                            hipStream_t s, const char *what)
+{
+    (void)ctx;
+    hipError_t e = hipMemcpyAsync(host_out, dev_out, sizeof(double) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, what);
+    return GALS_OK;
+}
+
+int gals_max_speed(gals_ctx *ctx, double t, double *out, void *workspace, size_t workspace_bytes_,
+                   void *stream)
+{
+    if (!ctx || !out || !workspace) return fail(GALS_EINVAL, "gals_max_speed: NULL argument");
+    if (!ctx->vel_set) return fail(GALS_EINVAL, "gals_max_speed: no velocity set");
+    if (!isfinite(t)) return fail(GALS_EINVAL, "gals_max_speed: t must be finite");
+    if (!aligned(workspace, 256) || workspace_bytes_ < workspace_bytes(ctx))
+        return fail(GALS_EINVAL, "gals_max_speed: workspace too small or misaligned");
+    if (ctx->device < 0) return fail(GALS_EINVAL, "gals_max_speed: host-only context (device -1)");
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "gals_max_speed: hipSetDevice");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gals_max_speed: pending HIP error");
+    double *part = (double *)((char *)workspace + partial_offset(ctx));
+    double *res = part + size_t(kRedBlocks) * kRedSlots;
+    hipStream_t s = (hipStream_t)stream;
+    e = launch_max_speed(ctx, time_factor(ctx->period, t), part, res, s);
+    if (e != hipSuccess) return hip_fail(e, "gals_max_speed: launch");
+    return finish_reduction(ctx, res, out, 1, s, "gals_max_speed: copy");
+}
+
+int gals_norms(gals_ctx *ctx, const void *phi, const void *grad, const void *phi_ref,
+               const void *grad_ref, double eps, double band, double *out, void *workspace,
+               size_t workspace_bytes_, void *stream)
+{
+    if (!ctx || !out || !workspace) return fail(GALS_EINVAL, "gals_norms: NULL argument");
+    if (!phi || !grad || !phi_ref || !grad_ref) return fail(GALS_EINVAL, "gals_norms: NULL state");
+    if (!isfinite(eps) || !(eps > 0.0) || !isfinite(band) || band < 0.0)
+        return fail(GALS_EINVAL, "gals_norms: eps must be > 0 and band >= 0");
+    if (!aligned(workspace, 256) || workspace_bytes_ < workspace_bytes(ctx))
+        return fail(GALS_EINVAL, "gals_norms: workspace too small or misaligned");
+    if (ctx->device < 0) return fail(GALS_EINVAL, "gals_norms: host-only context (device -1)");
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "gals_norms: hipSetDevice");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gals_norms: pending HIP error");
+    double *part = (double *)((char *)workspace + partial_offset(ctx));
+    double *res = part + size_t(kRedBlocks) * kRedSlots;
+    hipStream_t s = (hipStream_t)stream;
+    e = launch_norms(ctx, phi, grad, phi_ref, grad_ref, eps, band, part, res, s);
+    if (e != hipSuccess) return hip_fail(e, "gals_norms: launch");
+    int rc = finish_reduction(ctx, res, out, 8, s, "gals_norms: copy");
+    if (rc != GALS_OK) return rc;
+    double cellvol = 1.0;
+    for (int a = 0; a < ctx->dim; a++) cellvol *= ctx->g.h[a];
+    out[2] *= cellvol;
+    out[4] *= cellvol;
+    out[5] *= cellvol;
+    return GALS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Internal types shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gals.h"
+
+namespace gals {
+
+constexpr int kBlock = 256;          // threads per block of every node/point kernel
+constexpr int kMaxStreamModes = 64;  // user modes of GALS_VEL_STREAM_SIN
+constexpr int kMaxVecpotModes = 8;   // user modes of GALS_VEL_VECPOT_SIN
+constexpr int kRedBlocks = 1024;     // partial sums of the deterministic reductions
+constexpr int kRedSlots = 8;         // doubles per partial
+
+// Grid geometry, passed by value to kernels.
+struct Geom {
+    int dim;
+    int bc;          // GALS_BC_NEUMANN or GALS_BC_EXTRAPOLATE
+    double top[3];   // lo + ncell * h: the last node of each axis
+    int n[3];        // nodes per axis (1 for unused axes)
+    int nc[3];       // cells per axis
+    double lo[3];
+    double h[3];
+    double inv_h[3];
+    int64_t pitch;   // row pitch in elements
+    int64_t plane;   // plane stride in elements
+    int64_t nodes;   // n[0]*n[1]*n[2]
+};
+
+// Velocity parameters in the arithmetic type T, passed by value to kernels.
+// Stream-function modes are folded into dense 4x4 tables over (m,n) so that
+// every loop is fully unrolled with compile-time wavenumbers.
+template <typename T>
+struct Vel {
+    int kind;
+    // AFFINE: v = b + A (x - c); A[i*3+j] = dv_i/dx_j
+    T b[3];
+    double c[3];
+    T A[9];
+    // STREAM_SIN: S[m][n] = sum of a over modes with wavenumbers (m+1, n+1);
+    // SQ = S * (n+1) pi, SR = S * ((n+1) pi)^2
+    T S[4][4], SQ[4][4], SR[4][4];
+    // VECPOT_SIN, per mode: wavenumber indices (1..4) and 21 coefficients
+    // (amplitude times pi-scaled wavenumber products, see vel_vecpot)
+    int nvp;
+    int vpi[kMaxVecpotModes][3];
+    T vpc[kMaxVecpotModes][21];
+};
+
+// Per-step time factors c(t+dt), c(t), c(t+dt/2) of the three Shu-Osher stages.
+template <typename T>
+struct Stage {
+    T c1, c2, c3;
+};
+
+}  // namespace gals
+
+struct gals_ctx {
+    int dim;
+    int prec;
+    int mixed;
+    int device;
+    gals::Geom g;
+    bool vel_set;
+    int vel_kind;
+    double period;
+    gals::Vel<float> vf;
+    gals::Vel<double> vd;
+};
+
+namespace gals {
+
+// Launchers (kernels_*.hip). Each returns a hipError_t of the launch.
+hipError_t launch_step(const gals_ctx *ctx, const void *phi, const void *grad, void *phi_o,
+                       void *grad_o, double dt, double c1, double c2, double c3,
+                       hipStream_t s);
+hipError_t launch_eval(const gals_ctx *ctx, const void *phi, const void *grad, const double *pts,
+                       int64_t npts, void *val, void *normal, void *curv, hipStream_t s);
+hipError_t launch_norms(const gals_ctx *ctx, const void *phi, const void *grad,
+                        const void *phi_ref, const void *grad_ref, double eps, double band,
+                        double *partials, double *out, hipStream_t s);
+hipError_t launch_max_speed(const gals_ctx *ctx, double c, double *partials, double *out,
+                            hipStream_t s);
+
+}  // namespace gals

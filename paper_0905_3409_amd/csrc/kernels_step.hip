@@ -1,0 +1,170 @@
+// GA-CIR step kernels for gfx950: one thread per grid node, wave64, fused
+// trace + split + gather + Hermite + superconsistent gradient update.
+//
+// Each node reads only the old state (never updated in place) and writes its
+// new phi, psi with coalesced SoA stores. Departure cells are gathered through
+// the cache hierarchy, so any CFL number is handled by the same code path.
+#include "hermite.h"
+
+namespace gals {
+
+// Node index -> (i, j[, k]) with 32-bit arithmetic (the host caps the node
+// count below 2^31).
+template <typename T, int KIND, int MIX>
+__global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st, double dt,
+                                                   const T *__restrict__ phi,
+                                                   const T *__restrict__ grad,
+                                                   T *__restrict__ phi_o, T *__restrict__ grad_o)
+{
+    const unsigned id = blockIdx.x * kBlock + threadIdx.x;
+    if (id >= unsigned(g.nodes)) return;
+    const unsigned nx = unsigned(g.n[0]);
+    const int j = int(id / nx);
+    const int i = int(id - unsigned(j) * nx);
+    const T *gx = grad, *gy = grad + g.plane;
+
+    const double x[2] = {g.lo[0] + double(i) * g.h[0], g.lo[1] + double(j) * g.h[1]};
+    double X[2];
+    T J[4];
+    trace<T, 2, KIND>(p, st, dt, x, X, J);
+    const unsigned out = project_foot<2>(g, X);
+
+    int cell[2];
+    double xi[2];
+    split<2>(g, X, cell, xi);
+
+    T d[4][4];
+    gather2d<T, MIX>(g, phi, gx, gy, cell[0], cell[1], d);
+    Basis<T> bx, by;
+    basis<T, false>(T(xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
+    basis<T, false>(T(xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
+    T H, Hx, Hy;
+    hermite2d(d, bx, by, H, Hx, Hy);
+    if (out & 1u) Hx = T(0);
+    if (out & 2u) Hy = T(0);
+
+    const int64_t o = int64_t(j) * g.pitch + i;
+    phi_o[o] = H;
+    grad_o[o] = J[0] * Hx + J[2] * Hy;
+    grad_o[g.plane + o] = J[1] * Hx + J[3] * Hy;
+}
+
+template <typename T, int KIND, int MIX>
+__global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st, double dt,
+                                                   const T *__restrict__ phi,
+                                                   const T *__restrict__ grad,
+                                                   T *__restrict__ phi_o, T *__restrict__ grad_o)
+{
+    const unsigned id = blockIdx.x * kBlock + threadIdx.x;
+    if (id >= unsigned(g.nodes)) return;
+    const unsigned nx = unsigned(g.n[0]), ny = unsigned(g.n[1]);
+    const unsigned row = id / nx;
+    const int i = int(id - row * nx);
+    const int k = int(row / ny);
+    const int j = int(row - unsigned(k) * ny);
+    const T *gx = grad, *gy = grad + g.plane, *gz = grad + 2 * g.plane;
+
+    const double x[3] = {g.lo[0] + double(i) * g.h[0], g.lo[1] + double(j) * g.h[1],
+                         g.lo[2] + double(k) * g.h[2]};
+    double X[3];
+    T J[9];
+    trace<T, 3, KIND>(p, st, dt, x, X, J);
+    const unsigned out = project_foot<3>(g, X);
+
+    int cell[3];
+    double xi[3];
+    split<3>(g, X, cell, xi);
+
+    T d[8][8];
+    gather3d<T, MIX>(g, phi, gx, gy, gz, cell[0], cell[1], cell[2], d);
+    Basis<T> bx, by, bz;
+    basis<T, false>(T(xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
+    basis<T, false>(T(xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
+    basis<T, false>(T(xi[2]), T(g.h[2]), T(g.inv_h[2]), bz);
+    T H, Hx, Hy, Hz;
+    hermite3d(d, bx, by, bz, H, Hx, Hy, Hz);
+    if (out & 1u) Hx = T(0);
+    if (out & 2u) Hy = T(0);
+    if (out & 4u) Hz = T(0);
+
+    const int64_t o = (int64_t(k) * g.n[1] + j) * g.pitch + i;
+    phi_o[o] = H;
+    grad_o[o] = J[0] * Hx + J[3] * Hy + J[6] * Hz;
+    grad_o[g.plane + o] = J[1] * Hx + J[4] * Hy + J[7] * Hz;
+    grad_o[2 * g.plane + o] = J[2] * Hx + J[5] * Hy + J[8] * Hz;
+}
+
+template <typename T, int KIND, int MIX>
+static hipError_t launch_typed(const gals_ctx *ctx, const Vel<T> &p, const void *phi,
+                               const void *grad, void *phi_o, void *grad_o, double dt, double c1,
+                               double c2, double c3, hipStream_t s)
+{
+    const Stage<T> st{T(c1), T(c2), T(c3)};
+    const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock);
+    if (ctx->dim == 2) {
+        if constexpr (KIND == GALS_VEL_AFFINE || KIND == GALS_VEL_STREAM_SIN ||
+                      KIND == GALS_VEL_VORTEX || KIND == GALS_VEL_PSEUDO1D) {
+            hipLaunchKernelGGL((k_step2d<T, KIND, MIX>), dim3(blocks), dim3(kBlock), 0, s, ctx->g,
+                               p, st, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
+                               (T *)grad_o);
+            return hipGetLastError();
+        }
+    } else {
+        if constexpr (KIND == GALS_VEL_AFFINE || KIND == GALS_VEL_VECPOT_SIN ||
+                      KIND == GALS_VEL_LEVEQUE3D) {
+            hipLaunchKernelGGL((k_step3d<T, KIND, MIX>), dim3(blocks), dim3(kBlock), 0, s, ctx->g,
+                               p, st, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
+                               (T *)grad_o);
+            return hipGetLastError();
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int MIX>
+static hipError_t launch_kind(const gals_ctx *ctx, const Vel<T> &p, const void *phi,
+                              const void *grad, void *phi_o, void *grad_o, double dt, double c1,
+                              double c2, double c3, hipStream_t s)
+{
+    switch (ctx->vel_kind) {
+    case GALS_VEL_AFFINE:
+        return launch_typed<T, GALS_VEL_AFFINE, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt, c1,
+                                                     c2, c3, s);
+    case GALS_VEL_STREAM_SIN:
+        return launch_typed<T, GALS_VEL_STREAM_SIN, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt,
+                                                         c1, c2, c3, s);
+    case GALS_VEL_VECPOT_SIN:
+        return launch_typed<T, GALS_VEL_VECPOT_SIN, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt,
+                                                         c1, c2, c3, s);
+    case GALS_VEL_VORTEX:
+        return launch_typed<T, GALS_VEL_VORTEX, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt, c1,
+                                                     c2, c3, s);
+    case GALS_VEL_PSEUDO1D:
+        return launch_typed<T, GALS_VEL_PSEUDO1D, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt, c1,
+                                                       c2, c3, s);
+    case GALS_VEL_LEVEQUE3D:
+        return launch_typed<T, GALS_VEL_LEVEQUE3D, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt,
+                                                        c1, c2, c3, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step(const gals_ctx *ctx, const void *phi, const void *grad, void *phi_o,
+                       void *grad_o, double dt, double c1, double c2, double c3, hipStream_t s)
+{
+    if (ctx->prec == GALS_F32) {
+        if (ctx->mixed == GALS_MIXED_ZERO)
+            return launch_kind<float, GALS_MIXED_ZERO>(ctx, ctx->vf, phi, grad, phi_o, grad_o, dt,
+                                                       c1, c2, c3, s);
+        return launch_kind<float, GALS_MIXED_CENTRAL>(ctx, ctx->vf, phi, grad, phi_o, grad_o, dt,
+                                                      c1, c2, c3, s);
+    }
+    if (ctx->mixed == GALS_MIXED_ZERO)
+        return launch_kind<double, GALS_MIXED_ZERO>(ctx, ctx->vd, phi, grad, phi_o, grad_o, dt,
+                                                    c1, c2, c3, s);
+    return launch_kind<double, GALS_MIXED_CENTRAL>(ctx, ctx->vd, phi, grad, phi_o, grad_o, dt, c1,
+                                                   c2, c3, s);
+}
+
+}  // namespace gals

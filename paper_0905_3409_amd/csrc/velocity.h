@@ -1,0 +1,215 @@
+// Analytic velocity fields and their Jacobians on the device.
+//
+// Every field returns v(x) scaled by the stage time factor c, and the
+// Jacobian in the "J form" J[i*D + j] = d v_i / d x_j (the transpose of the
+// paper's deformation matrix of sec. 4). Positions arrive in FP64; the field
+// is evaluated in the arithmetic type T.
+#pragma once
+
+#include "gals_internal.h"
+
+namespace gals {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ __forceinline__ void sincospi_t(float x, float *s, float *c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincospi_t(double x, double *s, double *c) { sincospi(x, s, c); }
+__device__ __forceinline__ float exp_t(float x) { return expf(x); }
+__device__ __forceinline__ double exp_t(double x) { return exp(x); }
+
+// sin(k pi x), cos(k pi x) for k = 1..4 (index k-1): one sincospi, then the
+// Chebyshev recurrence s_{k+1} = 2 cos(pi x) s_k - s_{k-1}.
+template <typename T>
+__device__ __forceinline__ void sincos_multiples(T x, T s[4], T c[4])
+{
+    sincospi_t(x, &s[0], &c[0]);
+    const T t = T(2) * c[0];
+    s[1] = t * s[0];
+    c[1] = t * c[0] - T(1);
+    s[2] = t * s[1] - s[0];
+    c[2] = t * c[1] - c[0];
+    s[3] = t * s[2] - s[1];
+    c[3] = t * c[2] - c[1];
+}
+
+template <typename T>
+__device__ __forceinline__ T pick4(const T a[4], int i)
+{
+    // i is uniform across the wave (a kernel parameter)
+    return i == 1 ? a[0] : i == 2 ? a[1] : i == 3 ? a[2] : a[3];
+}
+
+// v = (-s_y, s_x) from a stream function's derivatives.
+template <typename T>
+__device__ __forceinline__ void from_stream(T sx, T sy, T sxx, T sxy, T syy, T c, T *v, T *J)
+{
+    v[0] = -c * sy;
+    v[1] = c * sx;
+    J[0] = -c * sxy;  // du/dx
+    J[1] = -c * syy;  // du/dy
+    J[2] = c * sxx;   // dv/dx
+    J[3] = c * sxy;   // dv/dy
+}
+
+template <typename T>
+__device__ __forceinline__ void vel_affine(const Vel<T> &p, const double *x, int D, T c, T *v,
+                                           T *J)
+{
+    T y[3];
+    for (int j = 0; j < D; j++) y[j] = T(x[j] - p.c[j]);
+    for (int i = 0; i < D; i++) {
+        T s = p.b[i];
+        for (int j = 0; j < D; j++) s += p.A[i * 3 + j] * y[j];
+        v[i] = c * s;
+        for (int j = 0; j < D; j++) J[i * D + j] = c * p.A[i * 3 + j];
+    }
+}
+
+// Stream function s = sum_{m,n} S[m][n] sin((m+1) pi x) sin((n+1) pi y).
+template <typename T>
+__device__ __forceinline__ void vel_stream(const Vel<T> &p, const double *x, T c, T *v, T *J)
+{
+    T sx[4], cx[4], sy[4], cy[4];
+    sincos_multiples(T(x[0]), sx, cx);
+    sincos_multiples(T(x[1]), sy, cy);
+    T fx = 0, fy = 0, fxx = 0, fyy = 0, fxy = 0;
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        T P = 0, Q = 0, R = 0;
+#pragma unroll
+        for (int n = 0; n < 4; n++) {
+            P += p.S[m][n] * sy[n];   // sum_n S sin(n pi y)
+            Q += p.SQ[m][n] * cy[n];  // d/dy
+            R += p.SR[m][n] * sy[n];  // -d2/dy2
+        }
+        const T km = T((m + 1) * kPi);
+        const T kc = km * cx[m];
+        fx += kc * P;
+        fy += sx[m] * Q;
+        fxx -= km * km * sx[m] * P;
+        fyy -= sx[m] * R;
+        fxy += kc * Q;
+    }
+    from_stream(fx, fy, fxx, fxy, fyy, c, v, J);
+}
+
+// s = sin^2(pi x) sin^2(pi y) / pi.
+template <typename T>
+__device__ __forceinline__ void vel_vortex(const double *x, T c, T *v, T *J)
+{
+    T s1x, c1x, s1y, c1y;
+    sincospi_t(T(x[0]), &s1x, &c1x);
+    sincospi_t(T(x[1]), &s1y, &c1y);
+    const T qx = s1x * s1x, qy = s1y * s1y;             // sin^2
+    const T s2x = T(2) * s1x * c1x, s2y = T(2) * s1y * c1y;  // sin(2 pi .)
+    const T c2x = T(1) - T(2) * qx, c2y = T(1) - T(2) * qy;  // cos(2 pi .)
+    const T pi = T(kPi);
+    from_stream(s2x * qy, qx * s2y, T(2) * pi * c2x * qy, pi * s2x * s2y, T(2) * pi * qx * c2y,
+                c, v, J);
+}
+
+// v = exp(e.x) e, e = (sqrt 2, sqrt pi) / sqrt(2 + pi).
+template <typename T>
+__device__ __forceinline__ void vel_pseudo1d(const double *x, T c, T *v, T *J)
+{
+    // e = (sqrt 2, sqrt pi) / sqrt(2 + pi), a unit vector
+    const T e0 = T(0.6236862429526107), e1 = T(0.7816747855416966);
+    const T E = c * exp_t(T(e0 * T(x[0]) + e1 * T(x[1])));
+    v[0] = E * e0;
+    v[1] = E * e1;
+    J[0] = E * e0 * e0;
+    J[1] = E * e0 * e1;
+    J[2] = J[1];
+    J[3] = E * e1 * e1;
+}
+
+// v = curl A, A = sum_k a_k sin(l pi x) sin(m pi y) sin(n pi z). Per mode the
+// seven products of sines (S) and cosines (C) in x, y, z are formed once and
+// combined with precomputed coefficients a_c K_i (K_j) (K = wavenumber * pi):
+//   vpc[0..5]  = az M, ay N, ax N, az L, ay L, ax M
+//   vpc[6..20] = az LM, ay LN, az MM, ay MN, az MN, ay NN, ax LN, az LL,
+//                ax MN, ax NN, az LN, ay LL, ax LM, ay LM, ax MM
+template <typename T>
+__device__ __forceinline__ void vel_vecpot(const Vel<T> &p, const double *x, T c, T *v, T *J)
+{
+    T sx[4], cx[4], sy[4], cy[4], sz[4], cz[4];
+    sincos_multiples(T(x[0]), sx, cx);
+    sincos_multiples(T(x[1]), sy, cy);
+    sincos_multiples(T(x[2]), sz, cz);
+    T vx = 0, vy = 0, vz = 0;
+    T j00 = 0, j01 = 0, j02 = 0, j10 = 0, j11 = 0, j12 = 0, j20 = 0, j21 = 0, j22 = 0;
+    for (int k = 0; k < p.nvp; k++) {
+        const T Sx = pick4(sx, p.vpi[k][0]), Cx = pick4(cx, p.vpi[k][0]);
+        const T Sy = pick4(sy, p.vpi[k][1]), Cy = pick4(cy, p.vpi[k][1]);
+        const T Sz = pick4(sz, p.vpi[k][2]), Cz = pick4(cz, p.vpi[k][2]);
+        const T ss = Sy * Sz, cs = Cy * Sz, sc = Sy * Cz, cc = Cy * Cz;
+        const T SSS = Sx * ss, SCS = Sx * cs, SSC = Sx * sc, SCC = Sx * cc;
+        const T CSS = Cx * ss, CCS = Cx * cs, CSC = Cx * sc;
+        const T *q = p.vpc[k];
+        vx += q[0] * SCS - q[1] * SSC;
+        vy += q[2] * SSC - q[3] * CSS;
+        vz += q[4] * CSS - q[5] * SCS;
+        j00 += q[6] * CCS - q[7] * CSC;
+        j01 -= q[8] * SSS + q[9] * SCC;
+        j02 += q[10] * SCC + q[11] * SSS;
+        j10 += q[12] * CSC + q[13] * SSS;
+        j11 += q[14] * SCC - q[6] * CCS;
+        j12 -= q[15] * SSS + q[16] * CSC;
+        j20 -= q[17] * SSS + q[18] * CCS;
+        j21 += q[19] * CCS + q[20] * SSS;
+        j22 += q[7] * CSC - q[14] * SCC;
+    }
+    v[0] = c * vx; v[1] = c * vy; v[2] = c * vz;
+    J[0] = c * j00; J[1] = c * j01; J[2] = c * j02;
+    J[3] = c * j10; J[4] = c * j11; J[5] = c * j12;
+    J[6] = c * j20; J[7] = c * j21; J[8] = c * j22;
+}
+
+// Divergence-free reading of the 3D deformation field of sec. 6.2:
+// u = 2 sin^2(pi x) sin(2 pi y) sin(2 pi z), v = -sin(2 pi x) sin^2(pi y) sin(2 pi z),
+// w = -sin(2 pi x) sin(2 pi y) sin^2(pi z).
+template <typename T>
+__device__ __forceinline__ void vel_leveque(const double *x, T c, T *v, T *J)
+{
+    T s1[3], c1[3], q[3], s2[3], c2[3];
+    for (int i = 0; i < 3; i++) {
+        sincospi_t(T(x[i]), &s1[i], &c1[i]);
+        q[i] = s1[i] * s1[i];
+        s2[i] = T(2) * s1[i] * c1[i];
+        c2[i] = T(1) - T(2) * q[i];
+    }
+    const T pi = T(kPi), tpi = T(2 * kPi);
+    v[0] = c * T(2) * q[0] * s2[1] * s2[2];
+    v[1] = -c * s2[0] * q[1] * s2[2];
+    v[2] = -c * s2[0] * s2[1] * q[2];
+    J[0] = c * tpi * s2[0] * s2[1] * s2[2];        // du/dx
+    J[1] = c * T(2) * q[0] * tpi * c2[1] * s2[2];  // du/dy
+    J[2] = c * T(2) * q[0] * s2[1] * tpi * c2[2];  // du/dz
+    J[3] = -c * tpi * c2[0] * q[1] * s2[2];        // dv/dx
+    J[4] = -c * s2[0] * pi * s2[1] * s2[2];        // dv/dy
+    J[5] = -c * s2[0] * q[1] * tpi * c2[2];        // dv/dz
+    J[6] = -c * tpi * c2[0] * s2[1] * q[2];        // dw/dx
+    J[7] = -c * s2[0] * tpi * c2[1] * q[2];        // dw/dy
+    J[8] = -c * s2[0] * s2[1] * pi * s2[2];        // dw/dz
+}
+
+// Dispatch on the compile-time field kind (D = space dimension).
+template <typename T, int D, int KIND>
+__device__ __forceinline__ void velocity(const Vel<T> &p, const double *x, T c, T *v, T *J)
+{
+    if constexpr (KIND == GALS_VEL_AFFINE) {
+        vel_affine(p, x, D, c, v, J);
+    } else if constexpr (KIND == GALS_VEL_STREAM_SIN) {
+        vel_stream(p, x, c, v, J);
+    } else if constexpr (KIND == GALS_VEL_VECPOT_SIN) {
+        vel_vecpot(p, x, c, v, J);
+    } else if constexpr (KIND == GALS_VEL_VORTEX) {
+        vel_vortex(x, c, v, J);
+    } else if constexpr (KIND == GALS_VEL_PSEUDO1D) {
+        vel_pseudo1d(x, c, v, J);
+    } else {
+        vel_leveque(x, c, v, J);
+    }
+}
+
+}  // namespace gals

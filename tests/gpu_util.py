@@ -1,0 +1,51 @@
+"""Shared helpers of the GPU parity tests (run through the C ABI)."""
+import numpy as np
+
+import oracle
+import paper_0905_3409_amd as pkg
+
+U32 = 2.0 ** -24  # FP32 unit roundoff
+TOL64 = 1e-12     # FP64 parity bar: normwise relative error per field
+
+
+def gpu_advance(dim, ncell, lo, hi, kind, params, period, phi0, psi0, t0, dt, steps,
+                dtype="float64", mixed=pkg.MIXED_CENTRAL, stream=None, bc=pkg.BC_NEUMANN):
+    import torch
+    g = pkg.Grid(ncell, lo, hi, dtype=dtype, mixed=mixed, bc=bc, device=0)
+    g.set_velocity(kind, params, period)
+    st = g.from_numpy(phi0, psi0)
+    g.advance(st, t0, dt, steps, stream=stream)
+    torch.cuda.synchronize()
+    return g.to_numpy(st)
+
+
+def oracle_advance(dim, ncell, lo, hi, kind, params, period, phi0, psi0, t0, dt, steps,
+                   mixed=pkg.MIXED_CENTRAL, bc=pkg.BC_NEUMANN):
+    return oracle.advance(dim, ncell, lo, hi, kind, params, period, phi0, psi0, t0, dt, steps,
+                          mixed_mode=mixed, bc=bc)
+
+
+def rel(a, b):
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+
+
+def rel_psi(g_psi, o_psi, o_phi, hmin):
+    """FP64 parity measure of psi: max |difference| over the magnitude of the
+    terms psi is summed from. The interpolant's gradient is a divided
+    difference of phi over one cell, so a rounding of phi (relative u to
+    |phi|) moves psi by u |phi| / h; two correct implementations that round
+    differently therefore differ by a few u max(|psi|, |phi|/h)."""
+    scale = max(np.max(np.abs(o_psi)), np.max(np.abs(o_phi)) / hmin)
+    return float(np.max(np.abs(g_psi - o_psi)) / scale)
+
+
+def fp32_tolerances(phi_ref, psi_ref, hmin, steps, k=32.0):
+    """Normwise FP32-vs-FP64 bounds. Each step rounds the stored state to FP32
+    (relative u) and the Hermite sums add a few roundings, so phi errs by about
+    k u per step. psi is a divided difference of phi over one cell, so the
+    absolute phi rounding u |phi| reappears in psi divided by h."""
+    n = max(1, steps)
+    tp = k * U32 * n
+    amp = 1.0 + np.max(np.abs(phi_ref)) / (hmin * max(np.max(np.abs(psi_ref)), 1e-300))
+    return tp, tp * amp

@@ -1,0 +1,158 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+that include/gals.h declares, and validates arguments on a host-only context
+(device -1) before touching HIP."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_0905_3409_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gals.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gals_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(pkg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = pkg.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def _ctx(dim=2, ncell=(10, 7, 5), prec=pkg.F32, mixed=pkg.MIXED_CENTRAL, bc=pkg.BC_NEUMANN,
+         device=-1):
+    L = pkg.lib()
+    ctx = ctypes.c_void_p()
+    nc = (ctypes.c_int64 * dim)(*ncell[:dim])
+    lo = (ctypes.c_double * dim)(*([0.0] * dim))
+    hi = (ctypes.c_double * dim)(*([1.0] * dim))
+    rc = L.gals_create(ctypes.byref(ctx), dim, nc, lo, hi, prec, mixed, bc, device)
+    return rc, ctx
+
+
+def test_create_validation():
+    L = pkg.lib()
+    assert _ctx(dim=4)[0] == pkg.EINVAL
+    assert _ctx(ncell=(1, 7, 5))[0] == pkg.EINVAL
+    assert _ctx(prec=3)[0] == pkg.EINVAL
+    assert _ctx(mixed=7)[0] == pkg.EINVAL
+    assert _ctx(bc=2)[0] == pkg.EINVAL
+    assert _ctx(bc=pkg.BC_EXTRAPOLATE)[0] == pkg.OK
+    assert _ctx(device=-2)[0] in (pkg.EINVAL, pkg.EHIP)
+    assert _ctx(dim=3, ncell=(2048, 2048, 1024))[0] == pkg.EINVAL  # >= 2^31 nodes
+    ctx = ctypes.c_void_p()
+    nc = (ctypes.c_int64 * 2)(8, 8)
+    lo = (ctypes.c_double * 2)(0.0, 1.0)
+    hi = (ctypes.c_double * 2)(1.0, 1.0)  # hi == lo on axis 1
+    assert L.gals_create(ctypes.byref(ctx), 2, nc, lo, hi, pkg.F32, 0, 0, -1) == pkg.EINVAL
+    assert b"axis 1" in L.gals_last_error()
+    rc, ctx = _ctx()
+    assert rc == pkg.OK
+    L.gals_destroy(ctx)
+    assert L.gals_destroy(None) == pkg.OK
+
+
+@pytest.mark.parametrize("dim,ncell,prec", [(2, (2048, 2048), pkg.F32), (2, (64, 64), pkg.F64),
+                                            (3, (256, 256, 256), pkg.F32), (3, (2, 3, 4), pkg.F64)])
+def test_layout_and_workspace(dim, ncell, prec):
+    L = pkg.lib()
+    rc, ctx = _ctx(dim=dim, ncell=ncell + (1,) * (3 - dim), prec=prec)
+    assert rc == pkg.OK
+    nodes = (ctypes.c_int64 * dim)()
+    pitch, plane = ctypes.c_int64(), ctypes.c_int64()
+    assert L.gals_layout(ctx, nodes, ctypes.byref(pitch), ctypes.byref(plane)) == pkg.OK
+    assert tuple(nodes) == tuple(n + 1 for n in ncell)
+    assert pitch.value % 64 == 0 and ncell[0] + 1 <= pitch.value < ncell[0] + 65
+    assert plane.value == pitch.value * int(np.prod([n + 1 for n in ncell[1:]]))
+    ws = ctypes.c_size_t()
+    assert L.gals_workspace_bytes(ctx, ctypes.byref(ws)) == pkg.OK
+    es = 4 if prec == pkg.F32 else 8
+    assert ws.value >= (1 + dim) * plane.value * es + 1025 * 8 * 8
+    assert ws.value % 256 == 0
+    L.gals_destroy(ctx)
+
+
+def _setvel(ctx, kind, params, period=0.0):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    ptr = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if p.size else None
+    return pkg.lib().gals_set_velocity(ctx, kind, ptr, p.size, period)
+
+
+def test_set_velocity_validation():
+    rc, c2 = _ctx(dim=2)
+    rc3, c3 = _ctx(dim=3)
+    assert _setvel(c2, pkg.AFFINE, np.zeros(8)) == pkg.OK
+    assert _setvel(c2, pkg.AFFINE, np.zeros(7)) == pkg.EINVAL
+    assert _setvel(c3, pkg.AFFINE, np.zeros(15)) == pkg.OK
+    assert _setvel(c2, pkg.STREAM_SIN, [0.1, 1, 4, 0.2, 3, 2]) == pkg.OK
+    assert _setvel(c2, pkg.STREAM_SIN, [0.1, 5, 1]) == pkg.ENOTSUP
+    assert _setvel(c2, pkg.STREAM_SIN, [0.1, 1.5, 1]) == pkg.ENOTSUP
+    assert _setvel(c2, pkg.STREAM_SIN, [0.1, 1]) == pkg.EINVAL
+    assert _setvel(c2, pkg.STREAM_SIN, np.tile([0.1, 1, 1], 65)) == pkg.ENOTSUP
+    assert _setvel(c3, pkg.STREAM_SIN, [0.1, 1, 1]) == pkg.EINVAL
+    assert _setvel(c3, pkg.VECPOT_SIN, [0.1, 0.2, 0.3, 1, 2, 3]) == pkg.OK
+    assert _setvel(c3, pkg.VECPOT_SIN, np.tile([0.1, 0.2, 0.3, 1, 2, 3], 9)) == pkg.ENOTSUP
+    assert _setvel(c2, pkg.VORTEX, [], 2.0) == pkg.OK
+    assert _setvel(c2, pkg.VORTEX, [1.0]) == pkg.EINVAL
+    assert _setvel(c2, pkg.PSEUDO1D, []) == pkg.OK
+    assert _setvel(c3, pkg.LEVEQUE3D, [], 2.5) == pkg.OK
+    assert _setvel(c2, pkg.LEVEQUE3D, []) == pkg.EINVAL
+    assert _setvel(c2, 99, []) == pkg.EINVAL
+    assert _setvel(c2, pkg.VORTEX, [], -1.0) == pkg.EINVAL
+    assert _setvel(c2, pkg.AFFINE, [np.nan] + [0.0] * 7) == pkg.EINVAL
+    pkg.lib().gals_destroy(c2)
+    pkg.lib().gals_destroy(c3)
+
+
+def test_advance_validation_on_host_only_context():
+    L = pkg.lib()
+    rc, ctx = _ctx(dim=2, ncell=(10, 7))
+    ws = ctypes.c_size_t()
+    L.gals_workspace_bytes(ctx, ctypes.byref(ws))
+    vp = ctypes.c_void_p
+    # fake, never dereferenced addresses: every call below fails validation first
+    phi, grad, w = vp(0x100000), vp(0x200000), vp(0x400000)
+    assert L.gals_advance(ctx, phi, grad, 0.0, 0.1, 1, w, ws.value, None) == pkg.EINVAL
+    assert b"no velocity" in L.gals_last_error()
+    assert _setvel(ctx, pkg.VORTEX, []) == pkg.OK
+    assert L.gals_advance(ctx, phi, grad, 0.0, 0.0, 1, w, ws.value, None) == pkg.EINVAL
+    assert L.gals_advance(ctx, phi, grad, 0.0, float("nan"), 1, w, ws.value, None) == pkg.EINVAL
+    assert L.gals_advance(ctx, phi, grad, float("inf"), 0.1, 1, w, ws.value, None) == pkg.EINVAL
+    assert L.gals_advance(ctx, phi, grad, 0.0, 0.1, -1, w, ws.value, None) == pkg.EINVAL
+    assert L.gals_advance(ctx, None, grad, 0.0, 0.1, 1, w, ws.value, None) == pkg.EINVAL
+    assert L.gals_advance(ctx, phi, grad, 0.0, 0.1, 1, w, ws.value - 1, None) == pkg.EINVAL
+    assert L.gals_advance(ctx, vp(0x100002), grad, 0.0, 0.1, 1, w, ws.value, None) == pkg.EINVAL
+    # overlapping phi and grad
+    assert L.gals_advance(ctx, phi, vp(0x100000 + 64), 0.0, 0.1, 1, w, ws.value, None) == pkg.EINVAL
+    assert b"overlap" in L.gals_last_error()
+    # overlapping state and workspace
+    assert L.gals_advance(ctx, phi, grad, 0.0, 0.1, 1, vp(0x200000), ws.value, None) == pkg.EINVAL
+    # steps == 0 is a no-op that succeeds without a device
+    assert L.gals_advance(ctx, phi, grad, 0.0, 0.1, 0, w, ws.value, None) == pkg.OK
+    # a valid call reaches the device check
+    assert L.gals_advance(ctx, phi, grad, 0.0, 0.1, 1, w, ws.value, None) == pkg.EINVAL
+    assert b"host-only" in L.gals_last_error()
+    assert L.gals_eval_points(ctx, phi, grad, None, 0, None, None, None, None) == pkg.OK
+    assert L.gals_eval_points(ctx, phi, grad, None, 5, None, None, None, None) == pkg.EINVAL
+    assert L.gals_eval_points(ctx, phi, grad, w, -1, None, None, None, None) == pkg.EINVAL
+    out = (ctypes.c_double * 8)()
+    assert L.gals_norms(ctx, phi, grad, phi, grad, 0.0, 0.1, out, w, ws.value, None) == pkg.EINVAL
+    assert L.gals_max_speed(ctx, 0.0, out, w, 8, None) == pkg.EINVAL
+    L.gals_destroy(ctx)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(pkg, "_lib", None)
+    monkeypatch.setattr(pkg, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        pkg.lib()

@@ -345,7 +345,7 @@ def test_translation_exact_for_total_degree_3(cfl):
     params = inputs.affine_params(vel, [0, 0], np.zeros((2, 2)))
     steps = 5
     ph, ps = oracle.advance(2, ncell, [0, 0], [1, 1], inputs.AFFINE, params, 0.0,
-                            phi, psi, 0.0, dt, steps)
+                            phi, psi, 0.0, dt, steps, bc=oracle.BC_EXTRAPOLATE)
     shift = [coords[a] - steps * dt * vel[a] for a in range(dim)]
     exp_phi, exp_psi = poly_state(p, shift)
     # feet that stay inside the grid: exact to rounding; feet that leave it
@@ -382,6 +382,60 @@ def test_integer_shift_is_exact_for_arbitrary_data(k, axis):
         np.testing.assert_array_equal(SH[:, k:, :], S[:, :-k, :])
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_neumann_inflow_one_step_closed_form(dim):
+    """Homogeneous Neumann at inflow (the boundary treatment of the paper's
+    tests, sec. 6.1): a foot that leaves the domain through x = 0 takes the
+    value at its projection onto the boundary, and the extension is constant
+    along the normal, so the new psi_x is 0. Constant velocity: J = I."""
+    rng = np.random.default_rng(130 + dim)
+    n = 9
+    ncell = (n,) * dim
+    p = Poly.random_total_degree(rng, dim, 3)
+    coords = inputs.node_grid(ncell)
+    phi, psi = poly_state(p, coords)
+    dt = 0.05
+    vel = np.zeros(dim)
+    vel[0] = 2.3 * (1.0 / n) / dt  # feet up to 2.3 cells outside x = 0
+    vel[1] = -0.4 * (1.0 / n) / dt
+    params = inputs.affine_params(vel, np.zeros(dim), np.zeros((dim, dim)))
+    ph, ps = oracle.advance(dim, ncell, np.zeros(dim), np.ones(dim), inputs.AFFINE, params,
+                            0.0, phi, psi, 0.0, dt, 1)
+    foot = [coords[a] - dt * vel[a] for a in range(dim)]
+    out = foot[0] < 0
+    inside = np.all([(f >= 0) & (f <= 1) for f in foot], axis=0)
+    proj = [np.clip(f, 0.0, 1.0) for f in foot]
+    ep, eg = poly_state(p, proj)
+    eg = eg.reshape(dim, -1)
+    ps = ps.reshape(dim, -1)
+    assert np.allclose(ph[inside], ep[inside], rtol=1e-12, atol=1e-12)
+    x_out = out & np.all([(f >= 0) & (f <= 1) for f in foot[1:]], axis=0)
+    assert x_out.sum() > 0
+    assert np.allclose(ph[x_out], ep[x_out], rtol=1e-12, atol=1e-12)
+    assert np.all(ps[0, x_out] == 0.0)
+    for a in range(1, dim):
+        assert np.allclose(ps[a, x_out], eg[a, x_out], rtol=1e-11, atol=1e-11)
+
+
+def test_neumann_keeps_rotation_bounded_where_extrapolation_grows():
+    """Rigid rotation at CFL 2.2 in the corners: extrapolating boundary cubics
+    2.2 cells out amplifies corner values step after step, while the Neumann
+    treatment keeps the level set bounded by its initial range."""
+    w = inputs.rotation_circle(seed=11)
+    args = (2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
+            w["phi0"], w["psi0"], 0.0, w["dt"], w["steps"])
+    ph_n, _ = oracle.advance(*args, bc=oracle.BC_NEUMANN)
+    ph_e, _ = oracle.advance(*args, bc=oracle.BC_EXTRAPOLATE)
+    m0 = np.abs(w["phi0"]).max()
+    assert np.abs(ph_n).max() <= 1.01 * m0
+    assert np.abs(ph_e).max() > 10 * m0
+    # the two treatments differ only where the corners' influence reaches; it
+    # spreads across the stream through the stencils and decays inwards
+    c = inputs.node_grid(w["ncell"])
+    disc = (c[0] - 0.5) ** 2 + (c[1] - 0.5) ** 2 < 0.3**2
+    assert np.abs(ph_n - ph_e)[disc].max() < 1e-8
+
+
 # ---------------------------------------------------------------------------
 # Superconsistency under affine flow (eq. superconsistency): polynomial data
 # of total degree 3 are advected exactly by the discrete affine foot map
@@ -406,7 +460,7 @@ def test_affine_flow_exact_on_polynomials(dim):
     params = inputs.affine_params(np.zeros(dim), c, A)
     dt, steps = 0.03, 4
     ph, ps = oracle.advance(dim, ncell, np.zeros(dim), np.ones(dim), inputs.AFFINE,
-                            params, 0.0, phi, psi, 0.0, dt, steps)
+                            params, 0.0, phi, psi, 0.0, dt, steps, bc=oracle.BC_EXTRAPOLATE)
     M = np.linalg.matrix_power(_rk3_matrix(A, dt), steps)
     foot = [c[i] + sum(M[i, j] * (coords[j] - c[j]) for j in range(dim)) for i in range(dim)]
     exp_phi = p(*foot)
