@@ -40,9 +40,19 @@ size_t state_bytes(const gals_ctx *c)
 
 size_t partial_offset(const gals_ctx *c) { return align256(state_bytes(c)); }
 
-size_t workspace_bytes(const gals_ctx *c)
+size_t coltab_offset(const gals_ctx *c)
 {
     return partial_offset(c) + align256(sizeof(double) * size_t(kRedBlocks + 1) * kRedSlots);
+}
+
+size_t rowtab_offset(const gals_ctx *c)
+{
+    return coltab_offset(c) + align256(size_t(kJet) * size_t(c->g.n[0]) * elem_size(c));
+}
+
+size_t workspace_bytes(const gals_ctx *c)
+{
+    return rowtab_offset(c) + align256(size_t(kJet) * size_t(c->g.n[1]) * elem_size(c));
 }
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb)
@@ -88,13 +98,20 @@ void fill_vel(Vel<T> &v, int kind, int dim, const double *p, int64_t np)
             const int m = int(p[3 * k + 1]), n = int(p[3 * k + 2]);
             S[m - 1][n - 1] += p[3 * k];
         }
+        int mmax = 0, nmax = 0;
         for (int m = 0; m < 4; m++)
             for (int n = 0; n < 4; n++) {
                 const double kn = (n + 1) * M_PI;
                 v.S[m][n] = T(S[m][n]);
                 v.SQ[m][n] = T(S[m][n] * kn);
                 v.SR[m][n] = T(S[m][n] * kn * kn);
+                if (S[m][n] != 0.0) {
+                    mmax = m + 1 > mmax ? m + 1 : mmax;
+                    nmax = n + 1 > nmax ? n + 1 : nmax;
+                }
             }
+        v.kx = T(M_PI * mmax);
+        v.ky = T(M_PI * nmax);
     } else if (kind == GALS_VEL_VECPOT_SIN) {
         v.nvp = int(np / 6);
         for (int k = 0; k < v.nvp; k++) {
@@ -291,13 +308,20 @@ int gals_advance(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
     void *bufs[2][2] = {{phi, grad}, {ws, ws + pb}};
+    void *coltab = nullptr, *rowtab = nullptr;
+    if (ctx->vel_kind == GALS_VEL_STREAM_SIN) {
+        coltab = ws + coltab_offset(ctx);
+        rowtab = ws + rowtab_offset(ctx);
+        e = launch_stream_tables(ctx, coltab, rowtab, s);
+        if (e != hipSuccess) return hip_fail(e, "gals_advance: table launch");
+    }
     for (int64_t n = 0; n < steps; n++) {
         const double t = t0 + double(n) * dt;
         const double c1 = time_factor(ctx->period, t + dt);
         const double c2 = time_factor(ctx->period, t);
         const double c3 = time_factor(ctx->period, t + 0.5 * dt);
         void **src = bufs[n & 1], **dst = bufs[(n + 1) & 1];
-        e = launch_step(ctx, src[0], src[1], dst[0], dst[1], dt, c1, c2, c3, s);
+        e = launch_step(ctx, src[0], src[1], dst[0], dst[1], dt, c1, c2, c3, coltab, rowtab, s);
         if (e != hipSuccess) return hip_fail(e, "gals_advance: step launch");
     }
     if (steps & 1) {

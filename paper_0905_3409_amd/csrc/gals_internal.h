@@ -13,6 +13,10 @@ constexpr int kMaxStreamModes = 64;  // user modes of GALS_VEL_STREAM_SIN
 constexpr int kMaxVecpotModes = 8;   // user modes of GALS_VEL_VECPOT_SIN
 constexpr int kRedBlocks = 1024;     // partial sums of the deterministic reductions
 constexpr int kRedSlots = 8;         // doubles per partial
+constexpr int kJet = 20;             // stream-function table entries per column / row
+// Taylor evaluation of the FP32 stream-function velocity at a stage point is
+// used while kx |dx| + ky |dy| stays below this bound (truncation < FP32 rounding)
+constexpr float kTaylorMax = 0.03f;
 
 // Grid geometry, passed by value to kernels.
 struct Geom {
@@ -42,6 +46,7 @@ struct Vel {
     // STREAM_SIN: S[m][n] = sum of a over modes with wavenumbers (m+1, n+1);
     // SQ = S * (n+1) pi, SR = S * ((n+1) pi)^2
     T S[4][4], SQ[4][4], SR[4][4];
+    T kx, ky;  // pi * largest wavenumber present along x, y
     // VECPOT_SIN, per mode: wavenumber indices (1..4) and 21 coefficients
     // (amplitude times pi-scaled wavenumber products, see vel_vecpot)
     int nvp;
@@ -75,7 +80,9 @@ namespace gals {
 // Launchers (kernels_*.hip). Each returns a hipError_t of the launch.
 hipError_t launch_step(const gals_ctx *ctx, const void *phi, const void *grad, void *phi_o,
                        void *grad_o, double dt, double c1, double c2, double c3,
-                       hipStream_t s);
+                       const void *coltab, const void *rowtab, hipStream_t s);
+// Per-column / per-row stream-function tables (GALS_VEL_STREAM_SIN only).
+hipError_t launch_stream_tables(const gals_ctx *ctx, void *coltab, void *rowtab, hipStream_t s);
 hipError_t launch_eval(const gals_ctx *ctx, const void *phi, const void *grad, const double *pts,
                        int64_t npts, void *val, void *normal, void *curv, hipStream_t s);
 hipError_t launch_norms(const gals_ctx *ctx, const void *phi, const void *grad,

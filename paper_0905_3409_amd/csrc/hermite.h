@@ -27,6 +27,27 @@ __device__ __forceinline__ void matmul_acc(const T *A, const T *B, T *C)
         }
 }
 
+// Superconsistent Jacobian of the Shu-Osher foot map from the velocity
+// Jacobians A0, A1, A2 at the three stage points (J form):
+// J1 = I - dt A0; J2 = I - dt (A0/4 + A1 J1 / 4);
+// J = I - dt (A0/6 + A1 J1 / 6 + 2 A2 J2 / 3).
+template <typename T, int D>
+__device__ __forceinline__ void jacobian_chain(const T *A0, const T *A1, const T *A2, T dtT, T *J)
+{
+    T J1[D * D], B1[D * D], J2[D * D], B2[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; k++) J1[k] = T((k % (D + 1)) == 0) - dtT * A0[k];
+    matmul_acc<T, D>(A1, J1, B1);
+#pragma unroll
+    for (int k = 0; k < D * D; k++)
+        J2[k] = T((k % (D + 1)) == 0) - dtT * (T(0.25) * A0[k] + T(0.25) * B1[k]);
+    matmul_acc<T, D>(A2, J2, B2);
+#pragma unroll
+    for (int k = 0; k < D * D; k++)
+        J[k] = T((k % (D + 1)) == 0) -
+               dtT * (A0[k] * T(1.0 / 6.0) + B1[k] * T(1.0 / 6.0) + B2[k] * T(2.0 / 3.0));
+}
+
 template <typename T, int D, int KIND>
 __device__ __forceinline__ void trace(const Vel<T> &p, const Stage<T> &st, double dt,
                                       const double *x, double *X, T *J)
@@ -48,20 +69,7 @@ __device__ __forceinline__ void trace(const Vel<T> &p, const Stage<T> &st, doubl
     for (int i = 0; i < D; i++)
         X[i] = x[i] - dt * (double(v0[i]) * (1.0 / 6.0) + double(v1[i]) * (1.0 / 6.0) +
                             double(v2[i]) * (2.0 / 3.0));
-    // Jacobian chain: J1 = I - dt A0; J2 = I - dt (A0/4 + A1 J1 / 4);
-    // J = I - dt (A0/6 + A1 J1 / 6 + 2 A2 J2 / 3)
-    T J1[D * D], B1[D * D], J2[D * D], B2[D * D];
-#pragma unroll
-    for (int k = 0; k < D * D; k++) J1[k] = T((k % (D + 1)) == 0) - dtT * A0[k];
-    matmul_acc<T, D>(A1, J1, B1);
-#pragma unroll
-    for (int k = 0; k < D * D; k++)
-        J2[k] = T((k % (D + 1)) == 0) - dtT * (T(0.25) * A0[k] + T(0.25) * B1[k]);
-    matmul_acc<T, D>(A2, J2, B2);
-#pragma unroll
-    for (int k = 0; k < D * D; k++)
-        J[k] = T((k % (D + 1)) == 0) -
-               dtT * (A0[k] * T(1.0 / 6.0) + B1[k] * T(1.0 / 6.0) + B2[k] * T(2.0 / 3.0));
+    jacobian_chain<T, D>(A0, A1, A2, dtT, J);
 }
 
 // ---------------------------------------------------------------------------

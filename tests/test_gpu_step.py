@@ -241,3 +241,19 @@ def test_nan_propagates_and_is_counted():
     assert out[6] > 0  # non-finite entries are reported
     phi, psi = g.to_numpy(st)
     assert out[6] == np.count_nonzero(~np.isfinite(phi)) + np.count_nonzero(~np.isfinite(psi))
+
+
+@pytest.mark.parametrize("n", [256, 512, 1024])
+def test_fp32_stream_taylor_and_exact_regimes(n):
+    """FP32 stream-function steps evaluate stages 2 and 3 from the node's
+    Taylor jet when the offset is small enough and exactly otherwise; n = 512
+    at CFL 0.8 mixes both within waves. Two steps against the oracle."""
+    w = inputs.stream_circles(seed=8, n=n, steps=n // 2)
+    args = (2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
+            w["phi0"], w["psi0"], 0.3, w["dt"], 2)
+    g = gpu_advance(*args, dtype="float32")
+    o = oracle_advance(*args)
+    tp, tg = fp32_tolerances(o[0], o[1], 1 / n, 2)
+    ep, eg = rel(g[0], o[0]), rel(g[1], o[1])
+    print(f"fp32 stream n={n}: phi {ep:.2e} (tol {tp:.1e}) psi {eg:.2e} (tol {tg:.1e})")
+    assert ep <= tp and eg <= tg
