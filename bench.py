@@ -27,6 +27,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GALS node-updates/s + HBM GB/s, FP32 vs FP64 GPU at matched L1 shape error"
 HBM_PEAK_GBPS = 8000.0
+# Non-packed FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+# (The 157.3 TFLOP/s datasheet figure needs packed FP32 instructions, which this
+# build does not emit.)
+VALU_F32_PEAK_TFLOPS = 78.6
+# Floating-point operations per node of the FP32 stream-function step as
+# formulated (jet + Taylor stages + Jacobian chain + FP64 foot + bicubic
+# value/gradient); FMA = 2. Breakdown in the design notes.
+ALG_FLOPS_PER_NODE = 523
+BYTES_PER_NODE = 24  # FP32 state: 3 planes read once + 3 planes written once
 
 
 def log(msg):
@@ -163,13 +172,16 @@ def main():
     res["fp32_l1_shape_error"] = n32[2]
     res["fp32_linf_band_error"] = n32[3]
 
-    bytes_per_node = 24  # FP32 state: 3 planes read once + 3 planes written once
-    achieved = nodes * bytes_per_node / (kernel_us * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBPS,
+    gbps = nodes * BYTES_PER_NODE / (kernel_us * 1e-6) / 1e9
+    tflops = nodes * ALG_FLOPS_PER_NODE / (kernel_us * 1e-6) / 1e12
+    roofline = {"bound": "alu", "achieved": tflops, "peak": VALU_F32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": tflops / VALU_F32_PEAK_TFLOPS,
                 "traffic": traffic_record("k_step2d_f32_stream_2048.md"),
-                "kernel": "k_step2d<float, STREAM_SIN, CENTRAL>",
-                "bytes_per_launch": nodes * bytes_per_node, "avg_launch_us": kernel_us}
+                "kernel": "k_step2d_stream<float, CENTRAL, taylor>",
+                "flops_per_launch": nodes * ALG_FLOPS_PER_NODE, "avg_launch_us": kernel_us,
+                "hbm_gbps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS,
+                "bytes_per_launch": nodes * BYTES_PER_NODE}
+    achieved = gbps
 
     # ------------------------------------------------------- CPU baseline
     cpu = None

@@ -105,7 +105,9 @@ enum {
  * answers layout, workspace and parameter-validation calls and rejects every
  * device call with EINVAL (no HIP call is made). EINVAL on dim not in {2,3},
  * ncell[a] < 2, hi <= lo, non-finite bounds, unknown prec, mixed_mode or bc, a
- * device outside [-1, device count), or 2^31 or more nodes; EHIP if the
+ * device outside [-1, device count), 2^31 or more nodes, or a padded state
+ * plane of 2 GiB or more (the kernels address a plane with 32-bit byte
+ * offsets); EHIP if the
  * device count cannot be read. */
 int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo,
                 const double *hi, int prec, int mixed_mode, int bc, int device);

@@ -177,7 +177,8 @@ int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo,
     g.nodes = nodes;
     g.pitch = (int64_t(g.n[0]) + 63) / 64 * 64;
     g.plane = g.pitch * g.n[1] * g.n[2];
-    if (g.plane > (int64_t(1) << 40)) return fail(GALS_EINVAL, "gals_create: plane too large");
+    if (g.plane * int64_t(prec == GALS_F32 ? 4 : 8) >= (int64_t(1) << 31))
+        return fail(GALS_EINVAL, "gals_create: a state plane of 2 GiB or more");
     if (device != -1) {
         int count = 0;
         hipError_t e = hipGetDeviceCount(&count);

@@ -118,6 +118,30 @@ __device__ __forceinline__ void split(const Geom &g, const double *X, int *cell,
 }
 
 // ---------------------------------------------------------------------------
+// Raw buffer loads: one descriptor per plane (base, size in bytes), 32-bit
+// element offsets, reads outside the plane return 0. The host keeps every
+// plane below 4 GiB.
+// ---------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+template <typename T>
+__device__ __forceinline__ Rsrc plane_rsrc(const T *base, int64_t elems)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(base), 0, int(elems * int64_t(sizeof(T))),
+                                             0x00020000);
+}
+
+__device__ __forceinline__ float bload(Rsrc r, unsigned elem, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, elem * 4u, 0, 0));
+}
+
+__device__ __forceinline__ double bload(Rsrc r, unsigned elem, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, elem * 8u, 0, 0));
+}
+
+// ---------------------------------------------------------------------------
 // Cross derivatives (sec. 2.3, approach (A)) at the two corners c, c+1 of a
 // cell from samples u[0..3] at nodes c-1..c+2 (clamped into [0, N]): central
 // differences inside, one-sided 3-point differences at node 0 and node N.
@@ -133,21 +157,22 @@ __device__ __forceinline__ void diff_pair(const T *u, bool lo_edge, bool hi_edge
 // Cell data d[v][alpha]: v = vertex bits (x = bit 0), alpha = derivative bits.
 // 2D alpha: 0 phi, 1 psi_x, 2 psi_y, 3 phi_xy.
 template <typename T, int MIX>
-__device__ __forceinline__ void gather2d(const Geom &g, const T *__restrict__ phi,
-                                         const T *__restrict__ gx, const T *__restrict__ gy,
-                                         int cx, int cy, T d[4][4])
+__device__ __forceinline__ void gather2d(const Geom &g, Rsrc rphi, Rsrc rgx, Rsrc rgy, int cx,
+                                         int cy, T d[4][4])
 {
-    const int64_t r0 = int64_t(cy) * g.pitch, r1 = r0 + g.pitch;
-    const int i0 = cx, i1 = cx + 1;
-    d[0][0] = phi[r0 + i0]; d[1][0] = phi[r0 + i1];
-    d[2][0] = phi[r1 + i0]; d[3][0] = phi[r1 + i1];
-    d[0][1] = gx[r0 + i0]; d[1][1] = gx[r0 + i1];
-    d[2][1] = gx[r1 + i0]; d[3][1] = gx[r1 + i1];
+    const unsigned r0 = unsigned(cy) * unsigned(g.pitch), r1 = r0 + unsigned(g.pitch);
+    const unsigned i0 = unsigned(cx), i1 = unsigned(cx) + 1u;
+    d[0][0] = bload(rphi, r0 + i0, T()); d[1][0] = bload(rphi, r0 + i1, T());
+    d[2][0] = bload(rphi, r1 + i0, T()); d[3][0] = bload(rphi, r1 + i1, T());
+    d[0][1] = bload(rgx, r0 + i0, T()); d[1][1] = bload(rgx, r0 + i1, T());
+    d[2][1] = bload(rgx, r1 + i0, T()); d[3][1] = bload(rgx, r1 + i1, T());
     if constexpr (MIX == GALS_MIXED_CENTRAL) {
-        const int im = cx > 0 ? cx - 1 : 0;
-        const int i2 = cx + 2 <= g.nc[0] ? cx + 2 : g.nc[0];
-        const T u0[4] = {gy[r0 + im], gy[r0 + i0], gy[r0 + i1], gy[r0 + i2]};
-        const T u1[4] = {gy[r1 + im], gy[r1 + i0], gy[r1 + i1], gy[r1 + i2]};
+        const unsigned im = unsigned(cx > 0 ? cx - 1 : 0);
+        const unsigned i2 = unsigned(cx + 2 <= g.nc[0] ? cx + 2 : g.nc[0]);
+        const T u0[4] = {bload(rgy, r0 + im, T()), bload(rgy, r0 + i0, T()),
+                         bload(rgy, r0 + i1, T()), bload(rgy, r0 + i2, T())};
+        const T u1[4] = {bload(rgy, r1 + im, T()), bload(rgy, r1 + i0, T()),
+                         bload(rgy, r1 + i1, T()), bload(rgy, r1 + i2, T())};
         d[0][2] = u0[1]; d[1][2] = u0[2];
         d[2][2] = u1[1]; d[3][2] = u1[2];
         const T inv2h = T(0.5 * g.inv_h[0]);
@@ -155,8 +180,8 @@ __device__ __forceinline__ void gather2d(const Geom &g, const T *__restrict__ ph
         diff_pair(u0, lo, hi, inv2h, d[0][3], d[1][3]);
         diff_pair(u1, lo, hi, inv2h, d[2][3], d[3][3]);
     } else {
-        d[0][2] = gy[r0 + i0]; d[1][2] = gy[r0 + i1];
-        d[2][2] = gy[r1 + i0]; d[3][2] = gy[r1 + i1];
+        d[0][2] = bload(rgy, r0 + i0, T()); d[1][2] = bload(rgy, r0 + i1, T());
+        d[2][2] = bload(rgy, r1 + i0, T()); d[3][2] = bload(rgy, r1 + i1, T());
         d[0][3] = d[1][3] = d[2][3] = d[3][3] = T(0);
     }
 }
@@ -165,37 +190,38 @@ __device__ __forceinline__ void gather2d(const Geom &g, const T *__restrict__ ph
 // 7 phi_xyz, with phi_xy = D_x psi_y, phi_xz = D_x psi_z, phi_yz = D_y psi_z,
 // phi_xyz = D_x D_y psi_z.
 template <typename T, int MIX>
-__device__ __forceinline__ void gather3d(const Geom &g, const T *__restrict__ phi,
-                                         const T *__restrict__ gx, const T *__restrict__ gy,
-                                         const T *__restrict__ gz, int c0, int c1, int c2,
-                                         T d[8][8])
+__device__ __forceinline__ void gather3d(const Geom &g, Rsrc rphi, Rsrc rgx, Rsrc rgy, Rsrc rgz,
+                                         int c0, int c1, int c2, T d[8][8])
 {
-    const int64_t P = g.pitch, S = g.pitch * g.n[1];
-    const int xs[4] = {c0 > 0 ? c0 - 1 : 0, c0, c0 + 1, c0 + 2 <= g.nc[0] ? c0 + 2 : g.nc[0]};
-    const int ys[4] = {c1 > 0 ? c1 - 1 : 0, c1, c1 + 1, c1 + 2 <= g.nc[1] ? c1 + 2 : g.nc[1]};
+    const unsigned P = unsigned(g.pitch), S = unsigned(g.pitch) * unsigned(g.n[1]);
+    const unsigned xs[4] = {unsigned(c0 > 0 ? c0 - 1 : 0), unsigned(c0), unsigned(c0 + 1),
+                            unsigned(c0 + 2 <= g.nc[0] ? c0 + 2 : g.nc[0])};
+    const unsigned ys[4] = {unsigned(c1 > 0 ? c1 - 1 : 0), unsigned(c1), unsigned(c1 + 1),
+                            unsigned(c1 + 2 <= g.nc[1] ? c1 + 2 : g.nc[1])};
     const bool xlo = c0 == 0, xhi = c0 + 1 == g.nc[0];
     const bool ylo = c1 == 0, yhi = c1 + 1 == g.nc[1];
     const T i2hx = T(0.5 * g.inv_h[0]), i2hy = T(0.5 * g.inv_h[1]);
 #pragma unroll
     for (int vz = 0; vz < 2; vz++) {
-        const int64_t zo = int64_t(c2 + vz) * S;
+        const unsigned zo = unsigned(c2 + vz) * S;
 #pragma unroll
         for (int vy = 0; vy < 2; vy++) {
-            const int64_t ro = zo + int64_t(ys[1 + vy]) * P;
+            const unsigned ro = zo + ys[1 + vy] * P;
 #pragma unroll
             for (int vx = 0; vx < 2; vx++) {
                 const int v = vx + 2 * vy + 4 * vz;
-                d[v][0] = phi[ro + xs[1 + vx]];
-                d[v][1] = gx[ro + xs[1 + vx]];
+                d[v][0] = bload(rphi, ro + xs[1 + vx], T());
+                d[v][1] = bload(rgx, ro + xs[1 + vx], T());
             }
             if constexpr (MIX == GALS_MIXED_CENTRAL) {
-                const T u[4] = {gy[ro + xs[0]], gy[ro + xs[1]], gy[ro + xs[2]], gy[ro + xs[3]]};
+                const T u[4] = {bload(rgy, ro + xs[0], T()), bload(rgy, ro + xs[1], T()),
+                                bload(rgy, ro + xs[2], T()), bload(rgy, ro + xs[3], T())};
                 d[2 * vy + 4 * vz][2] = u[1];
                 d[1 + 2 * vy + 4 * vz][2] = u[2];
                 diff_pair(u, xlo, xhi, i2hx, d[2 * vy + 4 * vz][3], d[1 + 2 * vy + 4 * vz][3]);
             } else {
-                d[2 * vy + 4 * vz][2] = gy[ro + xs[1]];
-                d[1 + 2 * vy + 4 * vz][2] = gy[ro + xs[2]];
+                d[2 * vy + 4 * vz][2] = bload(rgy, ro + xs[1], T());
+                d[1 + 2 * vy + 4 * vz][2] = bload(rgy, ro + xs[2], T());
                 d[2 * vy + 4 * vz][3] = d[1 + 2 * vy + 4 * vz][3] = T(0);
             }
         }
@@ -204,7 +230,7 @@ __device__ __forceinline__ void gather3d(const Geom &g, const T *__restrict__ ph
 #pragma unroll
             for (int jy = 0; jy < 4; jy++)
 #pragma unroll
-                for (int jx = 0; jx < 4; jx++) w[jy][jx] = gz[zo + int64_t(ys[jy]) * P + xs[jx]];
+                for (int jx = 0; jx < 4; jx++) w[jy][jx] = bload(rgz, zo + ys[jy] * P + xs[jx], T());
             T dy[2][4];  // D_y psi_z at rows c1, c1+1 for each x sample
 #pragma unroll
             for (int jx = 0; jx < 4; jx++) {
@@ -225,9 +251,9 @@ __device__ __forceinline__ void gather3d(const Geom &g, const T *__restrict__ ph
 #pragma unroll
             for (int vy = 0; vy < 2; vy++) {
                 const int b = 2 * vy + 4 * vz;
-                const int64_t ro = zo + int64_t(ys[1 + vy]) * P;
-                d[b][4] = gz[ro + xs[1]];
-                d[b + 1][4] = gz[ro + xs[2]];
+                const unsigned ro = zo + ys[1 + vy] * P;
+                d[b][4] = bload(rgz, ro + xs[1], T());
+                d[b + 1][4] = bload(rgz, ro + xs[2], T());
                 d[b][5] = d[b + 1][5] = d[b][6] = d[b + 1][6] = d[b][7] = d[b + 1][7] = T(0);
             }
         }

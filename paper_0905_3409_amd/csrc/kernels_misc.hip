@@ -30,12 +30,14 @@ __global__ __launch_bounds__(kBlock) void k_eval(Geom g, const T *__restrict__ p
     for (int a = 0; a < D; a++) basis<T, true>(T(xi[a]), T(g.h[a]), T(g.inv_h[a]), b[a]);
     if constexpr (D == 2) {
         T d[4][4];
-        gather2d<T, MIX>(g, phi, grad, grad + g.plane, cell[0], cell[1], d);
+        gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(grad, g.plane),
+                         plane_rsrc(grad + g.plane, g.plane), cell[0], cell[1], d);
         hermite2d_full(d, b[0], b[1], H, G, Hs);
     } else {
         T d[8][8];
-        gather3d<T, MIX>(g, phi, grad, grad + g.plane, grad + 2 * g.plane, cell[0], cell[1],
-                         cell[2], d);
+        gather3d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(grad, g.plane),
+                         plane_rsrc(grad + g.plane, g.plane), plane_rsrc(grad + 2 * g.plane, g.plane),
+                         cell[0], cell[1], cell[2], d);
         hermite3d_full(d, b[0], b[1], b[2], H, G, Hs);
     }
     T g2 = T(0), tr = T(0), gHg = T(0);

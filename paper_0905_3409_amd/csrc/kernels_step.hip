@@ -34,7 +34,8 @@ __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st
     split<2>(g, X, cell, xi);
 
     T d[4][4];
-    gather2d<T, MIX>(g, phi, gx, gy, cell[0], cell[1], d);
+    gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane), plane_rsrc(gy, g.plane),
+                     cell[0], cell[1], d);
     Basis<T> bx, by;
     basis<T, false>(T(xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
     basis<T, false>(T(xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
@@ -76,7 +77,8 @@ __global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st
     split<3>(g, X, cell, xi);
 
     T d[8][8];
-    gather3d<T, MIX>(g, phi, gx, gy, gz, cell[0], cell[1], cell[2], d);
+    gather3d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane), plane_rsrc(gy, g.plane),
+                     plane_rsrc(gz, g.plane), cell[0], cell[1], cell[2], d);
     Basis<T> bx, by, bz;
     basis<T, false>(T(xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
     basis<T, false>(T(xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
@@ -182,20 +184,22 @@ __device__ __forceinline__ void stream_jet(const T *u, const T *y, StreamJet<T> 
     J.t40 = sixth * d40; J.t13 = sixth * d13; J.t31 = sixth * d31; J.t04 = sixth * d04;
 }
 
-// (s_x, s_y, s_xx, s_xy, s_yy) at offset (dx, dy) from the node.
+// (s_x, s_y, s_xx, s_xy, s_yy) at offset (dx, dy) from the node, each
+// Taylor polynomial in nested (Horner) form.
 template <typename T>
 __device__ __forceinline__ void stream_taylor(const StreamJet<T> &J, T dx, T dy, T &sx, T &sy,
                                               T &sxx, T &sxy, T &syy)
 {
-    const T x2 = dx * dx, xy = dx * dy, y2 = dy * dy;
-    const T x3 = x2 * dx, x2y = x2 * dy, xy2 = dx * y2, y3 = y2 * dy;
-    sx = J.d10 + J.d20 * dx + J.d11 * dy + J.a30 * x2 + J.d21 * xy + J.a12 * y2 + J.t40 * x3 +
-         J.a31 * x2y + J.a22 * xy2 + J.t13 * y3;
-    sy = J.d01 + J.d11 * dx + J.d02 * dy + J.a21 * x2 + J.d12 * xy + J.a03 * y2 + J.t31 * x3 +
-         J.a22 * x2y + J.a13 * xy2 + J.t04 * y3;
-    sxx = J.d20 + J.d30 * dx + J.d21 * dy + J.a40 * x2 + J.a31 * (T(2) * xy) + J.a22 * y2;
-    sxy = J.d11 + J.d21 * dx + J.d12 * dy + J.a31 * x2 + J.a22 * (T(2) * xy) + J.a13 * y2;
-    syy = J.d02 + J.d12 * dx + J.d03 * dy + J.a22 * x2 + J.a13 * (T(2) * xy) + J.a04 * y2;
+    // s_x: d10 + dx (d20 + dx (a30 + t40 dx + a31 dy)) + dy (d11 + dx (d21 + a22 dy) + dy (a12 + t13 dy))
+    sx = J.d10 + dx * (J.d20 + dx * (J.a30 + J.t40 * dx + J.a31 * dy)) +
+         dy * (J.d11 + dx * (J.d21 + J.a22 * dy) + dy * (J.a12 + J.t13 * dy));
+    // s_y: d01 + dx (d11 + dx (a21 + t31 dx + a22 dy)) + dy (d02 + dx (d12 + a13 dy) + dy (a03 + t04 dy))
+    sy = J.d01 + dx * (J.d11 + dx * (J.a21 + J.t31 * dx + J.a22 * dy)) +
+         dy * (J.d02 + dx * (J.d12 + J.a13 * dy) + dy * (J.a03 + J.t04 * dy));
+    // second derivatives, degree 2: c0 + dx (cx + cxx dx + cxy dy) + dy (cy + cyy dy)
+    sxx = J.d20 + dx * (J.d30 + J.a40 * dx + T(2) * J.a31 * dy) + dy * (J.d21 + J.a22 * dy);
+    sxy = J.d11 + dx * (J.d21 + J.a31 * dx + T(2) * J.a22 * dy) + dy * (J.d12 + J.a13 * dy);
+    syy = J.d02 + dx * (J.d12 + J.a22 * dx + T(2) * J.a13 * dy) + dy * (J.d03 + J.a04 * dy);
 }
 
 // Velocity and its Jacobian at node + (dx, dy), stage factor c: the Taylor
@@ -218,14 +222,32 @@ __device__ __forceinline__ void stream_stage(const Vel<T> &p, const StreamJet<T>
 // GA-CIR step for the sine stream-function field. Launch: blocks of 64 x 4
 // threads; each wave owns 64 consecutive nodes of one row, so the row table
 // is read once per wave through scalar loads.
+// Workgroups are dealt to the 8 XCDs round-robin by id, and each XCD has its
+// own L2. Give XCD x a contiguous band of 64 x 4 tiles, walked row-group by
+// row-group, so the halo rows a tile gathers were just fetched into the same
+// L2 by the tile above. Returns false for ids past the last tile.
+__device__ __forceinline__ bool xcd_tile(unsigned tiles_x, unsigned tiles, unsigned &tx,
+                                         unsigned &ty)
+{
+    const unsigned per = (tiles + 7u) / 8u;
+    const unsigned t = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+    tx = t % tiles_x;
+    ty = t / tiles_x;
+    return t < tiles;
+}
+
 template <typename T, int MIX, bool TAYLOR>
 __global__ __launch_bounds__(kBlock) void k_step2d_stream(
     Geom g, Vel<T> p, Stage<T> st, double dt, const T *__restrict__ coltab,
     const T *__restrict__ rowtab, const T *__restrict__ phi, const T *__restrict__ grad,
     T *__restrict__ phi_o, T *__restrict__ grad_o)
 {
-    const int i = int(blockIdx.x) * 64 + int(threadIdx.x);
-    const int j = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * 4 + int(threadIdx.y));
+    const unsigned tiles_x = (unsigned(g.n[0]) + 63u) / 64u;
+    const unsigned tiles = tiles_x * ((unsigned(g.n[1]) + 3u) / 4u);
+    unsigned tx, ty;
+    if (!xcd_tile(tiles_x, tiles, tx, ty)) return;
+    const int i = int(tx) * 64 + int(threadIdx.x);
+    const int j = __builtin_amdgcn_readfirstlane(int(ty) * 4 + int(threadIdx.y));
     if (j >= g.n[1] || i >= g.n[0]) return;
     const T *gx = grad, *gy = grad + g.plane;
 
@@ -271,18 +293,15 @@ __global__ __launch_bounds__(kBlock) void k_step2d_stream(
             if (s[a] < 0.0) { s[a] = 0.0; out |= 1u << a; }
             else if (s[a] > double(g.nc[a])) { s[a] = double(g.nc[a]); out |= 1u << a; }
         }
-        const double fl = floor(s[a]);
-        const double top = double(g.nc[a] - 1);
-        int c;
-        if (fl >= 0.0 && fl <= top) c = int(fl);
-        else if (fl > top) c = g.nc[a] - 1;
-        else c = 0;
-        cell[a] = c;
-        xi[a] = s[a] - double(c);
+        // cell index clamped to [0, nc-1], local coordinate unclamped
+        const double fl = fmin(fmax(floor(s[a]), 0.0), double(g.nc[a] - 1));
+        cell[a] = int(fl);
+        xi[a] = s[a] - fl;
     }
 
     T d[4][4];
-    gather2d<T, MIX>(g, phi, gx, gy, cell[0], cell[1], d);
+    gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane), plane_rsrc(gy, g.plane),
+                     cell[0], cell[1], d);
     Basis<T> bx, by;
     basis<T, false>(T(xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
     basis<T, false>(T(xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
@@ -316,7 +335,8 @@ static hipError_t launch_stream(const gals_ctx *ctx, const Vel<T> &p, const void
                                 const void *rowtab, hipStream_t s)
 {
     const Stage<T> st{T(c1), T(c2), T(c3)};
-    const dim3 grid(unsigned((ctx->g.n[0] + 63) / 64), unsigned((ctx->g.n[1] + 3) / 4));
+    const unsigned tiles = unsigned((ctx->g.n[0] + 63) / 64) * unsigned((ctx->g.n[1] + 3) / 4);
+    const dim3 grid((tiles + 7u) / 8u * 8u);
     hipLaunchKernelGGL((k_step2d_stream<T, MIX, sizeof(T) == 4>), grid, dim3(64, 4), 0, s,
                        ctx->g, p, st, dt, (const T *)coltab, (const T *)rowtab, (const T *)phi,
                        (const T *)grad, (T *)phi_o, (T *)grad_o);
