@@ -15,6 +15,12 @@ FP64 path runs once beside it for the matched-error comparison.
 Prints one JSON line. Options: --gpus (only 1 is supported), --steps K,
 --warmup W, --no-cpu (skip the oracle baseline), --inner (time steps per
 benchmark step, default the workload's 1024).
+
+--workload batched times the many-problem case instead: 512 independent
+grids of round(2^U(5,9)) cells per side, each with its own circles and
+stream function, 256 steps of dt = 2/256 per benchmark step, advanced
+together (one persistent launch per step, the whole advance replayed from a
+captured hipGraph, wave shapes chosen by the autotuner first).
 """
 import argparse
 import json
@@ -42,20 +48,24 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the library sources; a committed traffic record applies only to
-    the kernel it was measured on."""
-    import glob
+# Sources each timed kernel is compiled from (plus the build flags): a
+# committed traffic record applies only while these are unchanged.
+STEP_HEADERS = ["gals_internal.h", "velocity.h", "hermite.h", "stream2d.h"]
+SINGLE_KERNEL_SOURCES = ["kernels_step.hip"] + STEP_HEADERS
+BATCH_KERNEL_SOURCES = ["batch.hip"] + STEP_HEADERS
+
+
+def kernel_source_hash(files):
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_0905_3409_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in sorted(files) + ["../build.py"]:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_0905_3409_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_record(profile_md):
+def traffic_record(profile_md, files):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
     scaled by the counters' reading of a plain copy; None if the kernel has
     changed since the counters were taken."""
@@ -65,7 +75,7 @@ def traffic_record(profile_md):
         return None
     m = re.search(r"traffic-record: src_hash=(\w+) fetch_kib=([\d.]+) write_kib=([\d.]+) "
                   r"fetch_scale=([\d.]+) write_scale=([\d.]+)", open(path).read())
-    if not m or m.group(1) != kernel_source_hash():
+    if not m or m.group(1) != kernel_source_hash(files):
         return None
     kib = float(m.group(2)) * float(m.group(4)) + float(m.group(3)) * float(m.group(5))
     return kib * 1024.0
@@ -79,6 +89,7 @@ def main():
     ap.add_argument("--inner", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", choices=["single", "batched"], default="single")
     ap.add_argument("--profile", action="store_true",
                     help="short FP32 advance plus a plain device copy of known size "
                          "(for calibrating rocprofv3 byte counters); prints no JSON")
@@ -95,6 +106,8 @@ def main():
     from paper_0905_3409_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "batched":
+        return bench_batched(args)
     dev = torch.device("cuda", 0)
     w = inputs.stream_circles()
     inner = args.inner or w["steps"]
@@ -176,7 +189,7 @@ def main():
     tflops = nodes * ALG_FLOPS_PER_NODE / (kernel_us * 1e-6) / 1e12
     roofline = {"bound": "alu", "achieved": tflops, "peak": VALU_F32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": tflops / VALU_F32_PEAK_TFLOPS,
-                "traffic": traffic_record("k_step2d_f32_stream_2048.md"),
+                "traffic": traffic_record("k_step2d_f32_stream_2048.md", SINGLE_KERNEL_SOURCES),
                 "kernel": "k_step2d_stream<float, CENTRAL, taylor>",
                 "flops_per_launch": nodes * ALG_FLOPS_PER_NODE, "avg_launch_us": kernel_us,
                 "hbm_gbps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS,
@@ -211,6 +224,107 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         **res,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_batched(args):
+    import numpy as np
+    import torch
+
+    import paper_0905_3409_amd as pkg
+    from paper_0905_3409_amd import inputs
+
+    dev = torch.device("cuda", 0)
+    w = inputs.batched_stream_circles()
+    probs = w["problems"]
+    inner = args.inner or w["steps"]
+    nodes = sum((p["ncell"][0] + 1) * (p["ncell"][1] + 1) for p in probs)
+    log(f"workload {w['name']}: {len(probs)} grids, {nodes} nodes, {inner} steps/bench step")
+    b = pkg.Batch([p["ncell"] for p in probs], dtype="float32")
+    for k, p in enumerate(probs):
+        b.set_velocity(k, w["kind"], p["params"], w["period"])
+    ref = b.from_numpy([(p["phi0"], p["psi0"]) for p in probs])
+    st = ref.clone()
+    s = torch.cuda.Stream()
+    if args.profile:
+        b.advance(st, 0.0, w["dt"], args.inner or 16)
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        log(f"profile: batched FP32 steps on {nodes} nodes, then a {nbytes} B device copy")
+        return 0
+    scratch = ref.clone()
+    tune_ms = b.autotune(scratch, w["dt"], steps=8)
+    del scratch
+    log(f"autotune: wave widths per class {b.get_tiles()}, {tune_ms:.3f} ms for 8 steps")
+
+    def bench_step(ev=None):
+        with torch.cuda.stream(s):
+            if ev is not None:
+                ev[0].record(s)
+            b.advance(st, 0.0, w["dt"], inner, graph=True, stream=s)
+            if ev is not None:
+                ev[1].record(s)
+        s.synchronize()
+
+    for _ in range(args.warmup):
+        bench_step()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        bench_step(events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    adv_ms = float(np.mean([a.elapsed_time(c) for a, c in events]))
+    kernel_us = adv_ms * 1e3 / inner  # per step launch (the table launch is < 0.1 %)
+    value = nodes * inner / (ms_per_step * 1e-3)
+    log(f"batched fp32: {ms_per_step:.2f} ms/bench step, advance {adv_ms:.2f} ms, "
+        f"{kernel_us:.2f} us per step launch, {value / 1e9:.2f} G node-upd/s")
+    tflops = nodes * ALG_FLOPS_PER_NODE / (kernel_us * 1e-6) / 1e12
+    gbps = nodes * BYTES_PER_NODE / (kernel_us * 1e-6) / 1e9
+    roofline = {"bound": "alu", "achieved": tflops, "peak": VALU_F32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": tflops / VALU_F32_PEAK_TFLOPS,
+                "traffic": traffic_record("k_batch_step_f32_512grids.md", BATCH_KERNEL_SOURCES),
+                "kernel": "k_batch_step<float, CENTRAL, taylor>",
+                "flops_per_launch": nodes * ALG_FLOPS_PER_NODE, "avg_launch_us": kernel_us,
+                "hbm_gbps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS,
+                "bytes_per_launch": nodes * BYTES_PER_NODE}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        k_cpu, sample = 8, list(range(0, len(probs), 8))
+        a = time.perf_counter()
+        for k in sample:
+            p = probs[k]
+            oracle.advance(2, p["ncell"], (0.0, 0.0), (1.0, 1.0), w["kind"], p["params"],
+                           w["period"], p["phi0"], p["psi0"], 0.0, w["dt"], k_cpu)
+        c = time.perf_counter()
+        snodes = sum((probs[k]["ncell"][0] + 1) * (probs[k]["ncell"][1] + 1) for k in sample)
+        cpu = {"value": snodes * k_cpu / (c - a), "unit": "node-updates/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"first {k_cpu} steps of every 8th of the 512 grids "
+                         f"({len(sample)} grids, {snodes} nodes; FP64 oracle, OpenMP), "
+                         f"{c - a:.1f} s"}
+        log(f"cpu oracle: {cpu['value'] / 1e6:.2f} M node-upd/s on {cpu['cores']} threads")
+    line = {
+        "metric": "GALS batched node-updates/s (512 uneven 2D grids, one launch per step)",
+        "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched_stream_circles: 512 grids, round(2^U(5,9)) cells per "
+                               "side, 4 circles and an 8-mode sine stream function each, "
+                               "256 steps of dt 2/256, CFL 0.8",
+                   "grids": len(probs), "nodes": nodes, "time_steps_per_step": inner,
+                   "wave_widths_per_class": b.get_tiles(), "graph": True, "seed": w["seed"]},
+        "hbm_gbps_algorithmic": gbps,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -171,6 +171,50 @@ int gals_norms(gals_ctx *ctx, const void *phi, const void *grad, const void *phi
                const void *grad_ref, double eps, double band, double *out,
                void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent 2D grids, each with its own sine stream-function
+ * field (GALS_VEL_STREAM_SIN; all share one period), advanced together by one
+ * persistent launch per step. The state of all problems is one buffer:
+ * problem p's phi plane starts at element offset[p], followed by its psi_x and
+ * psi_y planes (same pitch/plane conventions as a single grid). Throughput
+ * layer for the paper's method applied to many small problems; the per-node
+ * arithmetic is that of gals_advance, so results agree bit for bit.
+ * ------------------------------------------------------------------------- */
+typedef struct gals_batch gals_batch;
+
+/* Create a batch of nprob (1..65535) 2D grids: ncell[2p], ncell[2p+1] cells
+ * on [lo[2p], hi[2p]] x [lo[2p+1], hi[2p+1]], each plane under 2 GiB.
+ * device -1: host-only (layout and validation). The batch owns small device
+ * tables (problem descriptors and the tile list) that it uploads before its
+ * first advance; EINVAL for invalid sizes, ENOMEM when out of host memory. */
+int gals_batch_create(gals_batch **out, int64_t nprob, const int64_t *ncell, const double *lo,
+                      const double *hi, int prec, int mixed_mode, int bc, int device);
+int gals_batch_destroy(gals_batch *b);
+/* offset/pitch/plane: nprob entries each (elements); total_elems: buffer size. */
+int gals_batch_layout(const gals_batch *b, int64_t *offset, int64_t *pitch, int64_t *plane,
+                      int64_t *total_elems);
+int gals_batch_workspace_bytes(const gals_batch *b, size_t *bytes);
+/* Velocity of problem p: GALS_VEL_STREAM_SIN parameters as for a single grid
+ * (ENOTSUP for other kinds); every problem must use the same period. */
+int gals_batch_set_velocity(gals_batch *b, int64_t p, int kind, const double *params,
+                            int64_t nparams, double period);
+/* Wave shape per grid-size class (nodes per row <= 48, <= 96, <= 192, more):
+ * nodes per wave along x, 64, 32 or 16 (a wave covers 64/w rows). */
+int gals_batch_set_tiles(gals_batch *b, const int *wave_width_per_class);
+int gals_batch_get_tiles(const gals_batch *b, int *wave_width_per_class);
+/* Advance every problem by `steps` steps (as gals_advance). use_graph != 0
+ * captures the whole advance into a hipGraph on first use and replays it
+ * while (state, workspace, stream, t0, dt, steps) are unchanged; capture
+ * needs a non-null stream. Async. */
+int gals_batch_advance(gals_batch *b, void *state, double t0, double dt, int64_t steps,
+                       int use_graph, void *workspace, size_t workspace_bytes, void *stream);
+/* Choose the wave shape per size class by timing `steps` steps of each
+ * candidate on this batch (coordinate descent over the classes); keeps the
+ * fastest and returns its time in *best_ms. Advances `state` while timing:
+ * pass a scratch copy. Synchronises the stream. */
+int gals_batch_autotune(gals_batch *b, void *state, double dt, int64_t steps, void *workspace,
+                        size_t workspace_bytes, void *stream, double *best_ms);
+
 /* Thread-local text of the last error ("" if none). */
 const char *gals_last_error(void);
 

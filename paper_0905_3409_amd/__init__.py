@@ -31,7 +31,10 @@ AFFINE, STREAM_SIN, VECPOT_SIN, VORTEX, PSEUDO1D, LEVEQUE3D = 1, 2, 3, 4, 5, 6
 
 EXPORTS = ("gals_create", "gals_destroy", "gals_layout", "gals_workspace_bytes",
            "gals_set_velocity", "gals_advance", "gals_eval_points", "gals_max_speed",
-           "gals_norms", "gals_last_error")
+           "gals_norms", "gals_last_error", "gals_batch_create", "gals_batch_destroy",
+           "gals_batch_layout", "gals_batch_workspace_bytes", "gals_batch_set_velocity",
+           "gals_batch_set_tiles", "gals_batch_get_tiles", "gals_batch_advance",
+           "gals_batch_autotune")
 
 _lib = None
 
@@ -62,6 +65,16 @@ def lib():
     L.gals_eval_points.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp]
     L.gals_max_speed.argtypes = [vp, d, PD, vp, sz, vp]
     L.gals_norms.argtypes = [vp, vp, vp, vp, vp, d, d, PD, vp, sz, vp]
+    PI = ctypes.POINTER(ctypes.c_int)
+    L.gals_batch_create.argtypes = [ctypes.POINTER(vp), i64, P64, PD, PD, i, i, i, i]
+    L.gals_batch_destroy.argtypes = [vp]
+    L.gals_batch_layout.argtypes = [vp, P64, P64, P64, P64]
+    L.gals_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.gals_batch_set_velocity.argtypes = [vp, i64, i, PD, i64, d]
+    L.gals_batch_set_tiles.argtypes = [vp, PI]
+    L.gals_batch_get_tiles.argtypes = [vp, PI]
+    L.gals_batch_advance.argtypes = [vp, vp, d, d, i64, i, vp, sz, vp]
+    L.gals_batch_autotune.argtypes = [vp, vp, d, i64, vp, sz, vp, PD]
     L.gals_last_error.argtypes = []
     L.gals_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -238,3 +251,139 @@ class Grid:
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                _stream_handle(stream, self._dev())))
         return np.array(out[:])
+
+
+class Batch:
+    """Many independent 2D grids with sine stream-function fields, advanced
+    together (one persistent launch per step). ``ncells`` is a list of
+    (nx, ny) cell counts; every grid is the unit square unless lo/hi are
+    given per problem."""
+
+    def __init__(self, ncells, lo=None, hi=None, dtype="float32", mixed=MIXED_CENTRAL,
+                 bc=BC_NEUMANN, device=0):
+        self.nprob = len(ncells)
+        self.ncells = [tuple(int(v) for v in n) for n in ncells]
+        lo = np.zeros((self.nprob, 2)) if lo is None else np.asarray(lo, dtype=np.float64)
+        hi = np.ones((self.nprob, 2)) if hi is None else np.asarray(hi, dtype=np.float64)
+        if dtype in ("float32", "f32", np.float32):
+            self.prec = F32
+        elif dtype in ("float64", "f64", np.float64):
+            self.prec = F64
+        else:
+            raise ValueError(f"unsupported dtype {dtype!r}")
+        self.device = int(device)
+        nc = np.ascontiguousarray(self.ncells, dtype=np.int64).ravel()
+        lo = np.ascontiguousarray(lo, dtype=np.float64).ravel()
+        hi = np.ascontiguousarray(hi, dtype=np.float64).ravel()
+        self._b = ctypes.c_void_p()
+        P64 = ctypes.POINTER(ctypes.c_int64)
+        PD = ctypes.POINTER(ctypes.c_double)
+        check(lib().gals_batch_create(ctypes.byref(self._b), self.nprob,
+                                      nc.ctypes.data_as(P64), lo.ctypes.data_as(PD),
+                                      hi.ctypes.data_as(PD), self.prec, int(mixed), int(bc),
+                                      self.device))
+        self.offset = np.zeros(self.nprob, dtype=np.int64)
+        self.pitch = np.zeros(self.nprob, dtype=np.int64)
+        self.plane = np.zeros(self.nprob, dtype=np.int64)
+        total = ctypes.c_int64()
+        check(lib().gals_batch_layout(self._b, self.offset.ctypes.data_as(P64),
+                                      self.pitch.ctypes.data_as(P64),
+                                      self.plane.ctypes.data_as(P64), ctypes.byref(total)))
+        self.total_elems = total.value
+        wsb = ctypes.c_size_t()
+        check(lib().gals_batch_workspace_bytes(self._b, ctypes.byref(wsb)))
+        self.workspace_bytes = wsb.value
+        self._ws = None
+
+    def __del__(self):
+        b = getattr(self, "_b", None)
+        if b is not None and b.value and _lib is not None:
+            _lib.gals_batch_destroy(b)
+            self._b = None
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float32 if self.prec == F32 else torch.float64
+
+    def _dev(self):
+        import torch
+        return torch.device("cuda", self.device)
+
+    def num_nodes(self):
+        return sum((nx + 1) * (ny + 1) for nx, ny in self.ncells)
+
+    def set_velocity(self, p, kind, params, period=0.0):
+        arr = np.ascontiguousarray(params, dtype=np.float64)
+        check(lib().gals_batch_set_velocity(self._b, int(p), int(kind),
+                                            arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            arr.size, float(period)))
+
+    def set_tiles(self, widths):
+        arr = (ctypes.c_int * 4)(*[int(w) for w in widths])
+        check(lib().gals_batch_set_tiles(self._b, arr))
+
+    def get_tiles(self):
+        arr = (ctypes.c_int * 4)()
+        check(lib().gals_batch_get_tiles(self._b, arr))
+        return list(arr)
+
+    def empty_state(self):
+        import torch
+        return torch.zeros(self.total_elems, dtype=self.torch_dtype, device=self._dev())
+
+    def _views(self, state, p):
+        nx, ny = self.ncells[p]
+        o, pl, pt = int(self.offset[p]), int(self.plane[p]), int(self.pitch[p])
+        return [state[o + a * pl: o + (a + 1) * pl].view(ny + 1, pt)[:, : nx + 1] for a in range(3)]
+
+    def from_numpy(self, states):
+        """Device state from a list of dense (phi, psi) float64 pairs."""
+        import torch
+        st = self.empty_state()
+        for p, (phi, psi) in enumerate(states):
+            nx, ny = self.ncells[p]
+            planes = [np.asarray(phi).reshape(ny + 1, nx + 1)] + list(
+                np.asarray(psi).reshape(2, ny + 1, nx + 1))
+            for v, arr in zip(self._views(st, p), planes):
+                v.copy_(torch.from_numpy(np.ascontiguousarray(arr)).to(st.dtype))
+        return st
+
+    def to_numpy(self, state, p):
+        v = self._views(state, p)
+        phi = v[0].double().cpu().numpy().ravel()
+        psi = np.concatenate([v[1].double().cpu().numpy().ravel(),
+                              v[2].double().cpu().numpy().ravel()])
+        return phi, psi
+
+    def workspace(self):
+        import torch
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self._dev())
+        return self._ws
+
+    def _check_state(self, state):
+        if (state.dtype != self.torch_dtype or not state.is_cuda or not state.is_contiguous()
+                or state.numel() < self.total_elems or state.device.index != self.device):
+            raise ValueError("batch state must be a contiguous device tensor of "
+                             f"{self.total_elems} {self.torch_dtype} elements on cuda:{self.device}")
+
+    def advance(self, state, t0, dt, steps, graph=False, stream=None):
+        self._check_state(state)
+        ws = self.workspace()
+        check(lib().gals_batch_advance(self._b, ctypes.c_void_p(state.data_ptr()), float(t0),
+                                       float(dt), int(steps), int(bool(graph)),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream_handle(stream, self._dev())))
+        return state
+
+    def autotune(self, scratch_state, dt, steps=4, stream=None):
+        """Pick the wave shape per size class by timing; advances scratch_state."""
+        self._check_state(scratch_state)
+        ws = self.workspace()
+        best = ctypes.c_double()
+        check(lib().gals_batch_autotune(self._b, ctypes.c_void_p(scratch_state.data_ptr()),
+                                        float(dt), int(steps), ctypes.c_void_p(ws.data_ptr()),
+                                        ws.numel(), _stream_handle(stream, self._dev()),
+                                        ctypes.byref(best)))
+        return best.value

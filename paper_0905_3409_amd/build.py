@@ -8,13 +8,18 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgals.so")
-SOURCES = ["gals_api.hip", "kernels_step.hip", "kernels_misc.hip"]
+SOURCES = ["gals_api.hip", "gals_batch_api.hip", "kernels_step.hip", "kernels_misc.hip",
+           "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only within one source expression: the same code
+    # rounds the same way in every kernel it is inlined into (batched and
+    # single-grid runs agree bit for bit)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-command-line-argument",
 ]
 

@@ -12,14 +12,18 @@
 using namespace gals;
 
 namespace {
-
 thread_local char g_err[512] = "";
+}
+
+void gals::set_error_v(const char *fmt, va_list ap) { vsnprintf(g_err, sizeof(g_err), fmt, ap); }
+
+namespace {
 
 int fail(int code, const char *fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    gals::set_error_v(fmt, ap);
     va_end(ap);
     return code;
 }

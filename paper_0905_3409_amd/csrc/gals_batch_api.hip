@@ -1,0 +1,512 @@
+// Host runtime of the batched C ABI (include/gals.h, gals_batch_*): many
+// independent 2D grids with sine stream-function fields, one persistent
+// launch per step, optional hipGraph capture of a whole advance, and a
+// timing-based choice of the wave shape per grid-size class.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "gals_internal.h"
+
+using namespace gals;
+
+namespace {
+
+int bfail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    gals::set_error_v(fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int bhip(hipError_t e, const char *what)
+{
+    return bfail(GALS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+const unsigned kShapes[3] = {64u, 32u, 16u};
+
+// Grid-size class of a problem by nodes per row.
+int size_class(int n0) { return n0 <= 48 ? 0 : n0 <= 96 ? 1 : n0 <= 192 ? 2 : 3; }
+
+}  // namespace
+
+struct gals_batch {
+    int nprob = 0, prec = 0, mixed = 0, bc = 0, device = 0;
+    std::vector<Geom> g;
+    std::vector<int64_t> off, tab;
+    std::vector<double> S;  // 16 per problem: summed amplitudes per (m, n)
+    std::vector<char> vel_set;
+    double period = 0.0;
+    bool period_set = false;
+    int64_t total_elems = 0, tab_elems = 0;
+    int max_entries = 0;
+    unsigned class_wx[4] = {64u, 64u, 64u, 64u};
+    unsigned blocks = 0;
+    // device copies of the problem descriptors and the tile list
+    void *d_probs = nullptr;
+    void *d_probs64 = nullptr;
+    TileRef *d_tiles = nullptr;
+    unsigned ntiles = 0;
+    bool dirty = true;
+    // cached graph of one advance
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    void *gk_state = nullptr, *gk_ws = nullptr, *gk_stream = nullptr;
+    double gk_t0 = 0, gk_dt = 0;
+    int64_t gk_steps = -1;
+};
+
+namespace {
+
+size_t es(const gals_batch *b) { return b->prec == GALS_F32 ? 4 : 8; }
+
+size_t ws_bytes(const gals_batch *b)
+{
+    return size_t(round_up(b->total_elems * int64_t(es(b)), 256) +
+                  round_up(b->tab_elems * int64_t(es(b)), 256));
+}
+
+void drop_graph(gals_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->gk_steps = -1;
+}
+
+void free_device(gals_batch *b)
+{
+    if (b->d_probs) (void)hipFree(b->d_probs);
+    if (b->d_probs64 && b->d_probs64 != b->d_probs) (void)hipFree(b->d_probs64);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    b->d_probs = b->d_probs64 = nullptr;
+    b->d_tiles = nullptr;
+    b->ntiles = 0;
+}
+
+template <typename T>
+void fill_prob(const gals_batch *b, int p, BatchProb<T> &P)
+{
+    memset(&P, 0, sizeof(P));
+    P.g = b->g[p];
+    int mmax = 0, nmax = 0;
+    for (int m = 0; m < 4; m++)
+        for (int n = 0; n < 4; n++) {
+            const double a = b->S[16 * p + 4 * m + n];
+            const double kn = (n + 1) * M_PI;
+            P.S[m][n] = T(a);
+            P.SQ[m][n] = T(a * kn);
+            P.SR[m][n] = T(a * kn * kn);
+            if (a != 0.0) {
+                mmax = m + 1 > mmax ? m + 1 : mmax;
+                nmax = n + 1 > nmax ? n + 1 : nmax;
+            }
+        }
+    P.kx = T(M_PI * mmax);
+    P.ky = T(M_PI * nmax);
+    P.off = b->off[p];
+    P.tab = b->tab[p];
+    P.wx = b->class_wx[size_class(P.g.n[0])];
+    P.tiles_x = (unsigned(P.g.n[0]) + P.wx - 1u) / P.wx;
+}
+
+// Upload descriptors and the tile list (synchronous; never inside a capture).
+int upload(gals_batch *b)
+{
+    if (!b->dirty) return GALS_OK;
+    drop_graph(b);
+    free_device(b);
+    std::vector<BatchProb<float>> pf;
+    std::vector<BatchProb<double>> pd(b->nprob);
+    std::vector<TileRef> tiles;
+    if (b->prec == GALS_F32) pf.resize(b->nprob);
+    for (int p = 0; p < b->nprob; p++) {
+        fill_prob(b, p, pd[p]);
+        if (b->prec == GALS_F32) fill_prob(b, p, pf[p]);
+        const unsigned wx = pd[p].wx, rows = 4u * (64u / wx);
+        const unsigned nt = pd[p].tiles_x * ((unsigned(pd[p].g.n[1]) + rows - 1u) / rows);
+        if (uint64_t(tiles.size()) + nt > (uint64_t(1) << 31))
+            return bfail(GALS_EINVAL, "gals_batch: more than 2^31 tiles in one batch");
+        for (unsigned t = 0; t < nt; t++) tiles.push_back(TileRef{unsigned(p), t});
+    }
+    hipError_t e = hipMalloc(&b->d_probs64, sizeof(BatchProb<double>) * pd.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_probs64, pd.data(), sizeof(BatchProb<double>) * pd.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && b->prec == GALS_F32) {
+        e = hipMalloc(&b->d_probs, sizeof(BatchProb<float>) * pf.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_probs, pf.data(), sizeof(BatchProb<float>) * pf.size(),
+                          hipMemcpyHostToDevice);
+    } else if (e == hipSuccess) {
+        b->d_probs = b->d_probs64;
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_tiles, sizeof(TileRef) * tiles.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_device(b);
+        return bhip(e, "gals_batch: upload of problem descriptors");
+    }
+    b->ntiles = unsigned(tiles.size());
+    b->dirty = false;
+    return GALS_OK;
+}
+
+// Enqueue one advance on stream s (no synchronisation, capturable).
+hipError_t enqueue(gals_batch *b, void *state, void *ws, double t0, double dt, int64_t steps,
+                   hipStream_t s)
+{
+    char *w = (char *)ws;
+    void *copy = w;
+    void *tab = w + round_up(b->total_elems * int64_t(es(b)), 256);
+    hipError_t e = launch_batch_tables(b->prec, b->d_probs64, b->nprob, b->max_entries, tab, s);
+    if (e != hipSuccess) return e;
+    void *bufs[2] = {state, copy};
+    for (int64_t n = 0; n < steps; n++) {
+        const double t = t0 + double(n) * dt;
+        const double c1 = b->period > 0 ? cos(M_PI * (t + dt) / b->period) : 1.0;
+        const double c2 = b->period > 0 ? cos(M_PI * t / b->period) : 1.0;
+        const double c3 = b->period > 0 ? cos(M_PI * (t + 0.5 * dt) / b->period) : 1.0;
+        e = launch_batch_step(b->prec, b->mixed, b->d_probs, b->d_tiles, b->ntiles, dt, c1, c2,
+                              c3, tab, bufs[n & 1], bufs[(n + 1) & 1], b->blocks, s);
+        if (e != hipSuccess) return e;
+    }
+    if (steps & 1)
+        e = launch_batch_copy(b->prec, b->d_probs, b->d_tiles, b->ntiles, copy, state, b->blocks, s);
+    return e;
+}
+
+bool overlap(const void *a, size_t na, const void *c, size_t nc)
+{
+    const char *pa = (const char *)a, *pc = (const char *)c;
+    return pa < pc + nc && pc < pa + na;
+}
+
+struct DevGuard {
+    int old = -1;
+    hipError_t err = hipSuccess;
+    explicit DevGuard(int dev)
+    {
+        if (hipGetDevice(&old) != hipSuccess) old = -1;
+        if (old != dev) err = hipSetDevice(dev);
+    }
+    ~DevGuard()
+    {
+        int cur = -1;
+        if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+    }
+};
+
+int check_advance_args(gals_batch *b, void *state, double t0, double dt, int64_t steps, void *ws,
+                       size_t wsb)
+{
+    if (!b) return bfail(GALS_EINVAL, "gals_batch: NULL batch");
+    if (!state || !ws) return bfail(GALS_EINVAL, "gals_batch: NULL state or workspace");
+    for (int p = 0; p < b->nprob; p++)
+        if (!b->vel_set[p]) return bfail(GALS_EINVAL, "gals_batch: no velocity for problem %d", p);
+    if (!isfinite(dt) || !(dt > 0.0)) return bfail(GALS_EINVAL, "gals_batch: dt must be > 0");
+    if (!isfinite(t0)) return bfail(GALS_EINVAL, "gals_batch: t0 must be finite");
+    if (steps < 0) return bfail(GALS_EINVAL, "gals_batch: steps < 0");
+    if (wsb < ws_bytes(b)) return bfail(GALS_EINVAL, "gals_batch: workspace too small");
+    if ((uintptr_t(state) % es(b)) || (uintptr_t(ws) % 256))
+        return bfail(GALS_EINVAL, "gals_batch: misaligned state or workspace");
+    if (overlap(state, size_t(b->total_elems) * es(b), ws, wsb))
+        return bfail(GALS_EINVAL, "gals_batch: state and workspace overlap");
+    return GALS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gals_batch_create(gals_batch **out, int64_t nprob, const int64_t *ncell, const double *lo,
+                      const double *hi, int prec, int mixed_mode, int bc, int device)
+{
+    if (!out) return bfail(GALS_EINVAL, "gals_batch_create: out is NULL");
+    *out = nullptr;
+    // the table launch puts the problem index in the grid's y dimension
+    if (nprob < 1 || nprob > 65535) return bfail(GALS_EINVAL, "gals_batch_create: nprob must be 1..65535");
+    if (!ncell || !lo || !hi) return bfail(GALS_EINVAL, "gals_batch_create: NULL ncell/lo/hi");
+    if (prec != GALS_F32 && prec != GALS_F64) return bfail(GALS_EINVAL, "gals_batch_create: precision");
+    if (mixed_mode != GALS_MIXED_CENTRAL && mixed_mode != GALS_MIXED_ZERO)
+        return bfail(GALS_EINVAL, "gals_batch_create: mixed-derivative mode");
+    if (bc != GALS_BC_NEUMANN && bc != GALS_BC_EXTRAPOLATE)
+        return bfail(GALS_EINVAL, "gals_batch_create: boundary treatment");
+    gals_batch *b = new (std::nothrow) gals_batch;
+    if (!b) return bfail(GALS_ENOMEM, "gals_batch_create: out of host memory");
+    b->nprob = int(nprob);
+    b->prec = prec;
+    b->mixed = mixed_mode;
+    b->bc = bc;
+    b->device = device;
+    b->g.resize(nprob);
+    b->off.resize(nprob);
+    b->tab.resize(nprob);
+    b->S.assign(16 * nprob, 0.0);
+    b->vel_set.assign(nprob, 0);
+    const int64_t esz = prec == GALS_F32 ? 4 : 8;
+    int64_t offs = 0, tabs = 0;
+    for (int64_t p = 0; p < nprob; p++) {
+        Geom &g = b->g[p];
+        memset(&g, 0, sizeof(g));
+        g.dim = 2;
+        g.bc = bc;
+        g.n[2] = 1;
+        g.h[2] = g.inv_h[2] = 1.0;
+        for (int a = 0; a < 2; a++) {
+            const int64_t nc = ncell[2 * p + a];
+            const double l = lo[2 * p + a], h = hi[2 * p + a];
+            if (nc < 2 || nc > (1 << 20) || !isfinite(l) || !isfinite(h) || !(h > l)) {
+                delete b;
+                return bfail(GALS_EINVAL, "gals_batch_create: problem %lld axis %d invalid",
+                             (long long)p, a);
+            }
+            g.nc[a] = int(nc);
+            g.n[a] = int(nc + 1);
+            g.lo[a] = l;
+            g.h[a] = (h - l) / double(nc);
+            g.inv_h[a] = 1.0 / g.h[a];
+            g.top[a] = l + double(nc) * g.h[a];
+        }
+        g.nodes = int64_t(g.n[0]) * g.n[1];
+        g.pitch = round_up(g.n[0], 64);
+        g.plane = g.pitch * g.n[1];
+        if (g.plane * esz >= (int64_t(1) << 31)) {
+            delete b;
+            return bfail(GALS_EINVAL, "gals_batch_create: problem %lld plane of 2 GiB or more",
+                         (long long)p);
+        }
+        b->off[p] = offs;
+        offs += 3 * g.plane;  // planes are multiples of 64 elements: alignment kept
+        b->tab[p] = tabs;
+        tabs += round_up(int64_t(g.n[0] + g.n[1]) * kJet, 64);
+        const int entries = g.n[0] + g.n[1];
+        if (entries > b->max_entries) b->max_entries = entries;
+    }
+    b->total_elems = offs;
+    b->tab_elems = tabs;
+    if (device >= 0) {
+        int count = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e == hipSuccess && (device >= count)) e = hipErrorInvalidDevice;
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+        if (e == hipSuccess) {
+            DevGuard dg(device);
+            e = dg.err;
+            if (e == hipSuccess) e = batch_step_blocks_per_cu(prec, mixed_mode, &per_cu);
+        }
+        if (e != hipSuccess) {
+            delete b;
+            return bhip(e, "gals_batch_create: device query");
+        }
+        // all blocks resident at once; a multiple of the 8 XCDs
+        per_cu = per_cu < 1 ? 1 : per_cu > 8 ? 8 : per_cu;
+        b->blocks = (unsigned(cus) * unsigned(per_cu)) / 8u * 8u;
+        if (b->blocks < 8u) b->blocks = 8u;
+    } else if (device != -1) {
+        delete b;
+        return bfail(GALS_EINVAL, "gals_batch_create: device %d", device);
+    } else {
+        b->blocks = 2048;
+    }
+    *out = b;
+    return GALS_OK;
+}
+
+int gals_batch_destroy(gals_batch *b)
+{
+    if (!b) return GALS_OK;
+    if (b->device >= 0) {
+        DevGuard dg(b->device);
+        drop_graph(b);
+        free_device(b);
+    }
+    delete b;
+    return GALS_OK;
+}
+
+int gals_batch_layout(const gals_batch *b, int64_t *offset, int64_t *pitch, int64_t *plane,
+                      int64_t *total_elems)
+{
+    if (!b) return bfail(GALS_EINVAL, "gals_batch_layout: NULL batch");
+    for (int p = 0; p < b->nprob; p++) {
+        if (offset) offset[p] = b->off[p];
+        if (pitch) pitch[p] = b->g[p].pitch;
+        if (plane) plane[p] = b->g[p].plane;
+    }
+    if (total_elems) *total_elems = b->total_elems;
+    return GALS_OK;
+}
+
+int gals_batch_workspace_bytes(const gals_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return bfail(GALS_EINVAL, "gals_batch_workspace_bytes: NULL argument");
+    *bytes = ws_bytes(b);
+    return GALS_OK;
+}
+
+int gals_batch_set_velocity(gals_batch *b, int64_t p, int kind, const double *params,
+                            int64_t nparams, double period)
+{
+    if (!b) return bfail(GALS_EINVAL, "gals_batch_set_velocity: NULL batch");
+    if (p < 0 || p >= b->nprob) return bfail(GALS_EINVAL, "gals_batch_set_velocity: problem index");
+    if (kind != GALS_VEL_STREAM_SIN)
+        return bfail(GALS_ENOTSUP, "gals_batch_set_velocity: batches take GALS_VEL_STREAM_SIN fields");
+    if (!params || nparams <= 0 || nparams % 3 || nparams / 3 > kMaxStreamModes)
+        return bfail(GALS_EINVAL, "gals_batch_set_velocity: 3 parameters per mode, 1..64 modes");
+    if (!isfinite(period) || period < 0.0)
+        return bfail(GALS_EINVAL, "gals_batch_set_velocity: period must be finite and >= 0");
+    if (b->period_set && period != b->period)
+        return bfail(GALS_EINVAL, "gals_batch_set_velocity: all problems share one period");
+    double S[16] = {0};
+    for (int64_t k = 0; k < nparams / 3; k++) {
+        const double a = params[3 * k], m = params[3 * k + 1], n = params[3 * k + 2];
+        if (!isfinite(a)) return bfail(GALS_EINVAL, "gals_batch_set_velocity: non-finite amplitude");
+        if (m != floor(m) || n != floor(n) || m < 1 || m > 4 || n < 1 || n > 4)
+            return bfail(GALS_ENOTSUP, "gals_batch_set_velocity: wavenumbers must be integers in 1..4");
+        S[4 * (int(m) - 1) + int(n) - 1] += a;
+    }
+    memcpy(&b->S[16 * p], S, sizeof(S));
+    b->vel_set[p] = 1;
+    b->period = period;
+    b->period_set = true;
+    b->dirty = true;
+    return GALS_OK;
+}
+
+int gals_batch_set_tiles(gals_batch *b, const int *wave_width_per_class)
+{
+    if (!b || !wave_width_per_class) return bfail(GALS_EINVAL, "gals_batch_set_tiles: NULL argument");
+    for (int c = 0; c < 4; c++) {
+        const int w = wave_width_per_class[c];
+        if (w != 64 && w != 32 && w != 16)
+            return bfail(GALS_EINVAL, "gals_batch_set_tiles: wave width must be 64, 32 or 16");
+    }
+    for (int c = 0; c < 4; c++) b->class_wx[c] = unsigned(wave_width_per_class[c]);
+    b->dirty = true;
+    return GALS_OK;
+}
+
+int gals_batch_get_tiles(const gals_batch *b, int *wave_width_per_class)
+{
+    if (!b || !wave_width_per_class) return bfail(GALS_EINVAL, "gals_batch_get_tiles: NULL argument");
+    for (int c = 0; c < 4; c++) wave_width_per_class[c] = int(b->class_wx[c]);
+    return GALS_OK;
+}
+
+int gals_batch_advance(gals_batch *b, void *state, double t0, double dt, int64_t steps,
+                       int use_graph, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int rc = check_advance_args(b, state, t0, dt, steps, workspace, workspace_bytes);
+    if (rc != GALS_OK) return rc;
+    if (steps == 0) return GALS_OK;
+    if (b->device < 0) return bfail(GALS_EINVAL, "gals_batch_advance: host-only batch (device -1)");
+    if (use_graph && !stream)
+        return bfail(GALS_EINVAL, "gals_batch_advance: graph capture needs a non-null stream");
+    DevGuard dg(b->device);
+    if (dg.err != hipSuccess) return bhip(dg.err, "gals_batch_advance: hipSetDevice");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bhip(e, "gals_batch_advance: pending HIP error");
+    rc = upload(b);
+    if (rc != GALS_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (!use_graph) {
+        e = enqueue(b, state, workspace, t0, dt, steps, s);
+        return e == hipSuccess ? GALS_OK : bhip(e, "gals_batch_advance: launch");
+    }
+    const bool hit = b->gexec && b->gk_state == state && b->gk_ws == workspace &&
+                     b->gk_stream == stream && b->gk_t0 == t0 && b->gk_dt == dt &&
+                     b->gk_steps == steps;
+    if (!hit) {
+        drop_graph(b);
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return bhip(e, "gals_batch_advance: begin capture");
+        hipError_t le = enqueue(b, state, workspace, t0, dt, steps, s);
+        e = hipStreamEndCapture(s, &b->graph);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(b);
+            return bhip(e, "gals_batch_advance: graph capture");
+        }
+        b->gk_state = state;
+        b->gk_ws = workspace;
+        b->gk_stream = stream;
+        b->gk_t0 = t0;
+        b->gk_dt = dt;
+        b->gk_steps = steps;
+    }
+    e = hipGraphLaunch(b->gexec, s);
+    return e == hipSuccess ? GALS_OK : bhip(e, "gals_batch_advance: graph launch");
+}
+
+int gals_batch_autotune(gals_batch *b, void *state, double dt, int64_t steps, void *workspace,
+                        size_t workspace_bytes, void *stream, double *best_ms)
+{
+    int rc = check_advance_args(b, state, 0.0, dt, steps, workspace, workspace_bytes);
+    if (rc != GALS_OK) return rc;
+    if (steps < 1) return bfail(GALS_EINVAL, "gals_batch_autotune: steps must be >= 1");
+    if (b->device < 0) return bfail(GALS_EINVAL, "gals_batch_autotune: host-only batch");
+    DevGuard dg(b->device);
+    if (dg.err != hipSuccess) return bhip(dg.err, "gals_batch_autotune: hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return bhip(hipGetLastError(), "gals_batch_autotune: event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return bhip(hipGetLastError(), "gals_batch_autotune: event");
+    }
+    bool present[4] = {false, false, false, false};
+    for (int p = 0; p < b->nprob; p++) present[size_class(b->g[p].n[0])] = true;
+    auto time_once = [&](float *ms) -> int {
+        int r = upload(b);
+        if (r != GALS_OK) return r;
+        hipError_t e = enqueue(b, state, workspace, 0.0, dt, 1, s);  // warm
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = enqueue(b, state, workspace, 0.0, dt, steps, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+        return e == hipSuccess ? GALS_OK : bhip(e, "gals_batch_autotune: timing");
+    };
+    float best = 0.0f;
+    rc = time_once(&best);
+    for (int c = 0; c < 4 && rc == GALS_OK; c++) {
+        if (!present[c]) continue;
+        const unsigned keep = b->class_wx[c];
+        unsigned pick = keep;
+        for (unsigned w : kShapes) {
+            if (w == keep) continue;
+            b->class_wx[c] = w;
+            b->dirty = true;
+            float ms = 0.0f;
+            rc = time_once(&ms);
+            if (rc != GALS_OK) break;
+            if (ms < best) {
+                best = ms;
+                pick = w;
+            }
+        }
+        b->class_wx[c] = pick;
+        b->dirty = true;
+    }
+    if (rc == GALS_OK) rc = upload(b);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == GALS_OK && best_ms) *best_ms = double(best);
+    return rc;
+}
+
+}  // extern "C"

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stdarg.h>
 #include <stdint.h>
 
 #include "../../include/gals.h"
@@ -60,6 +61,26 @@ struct Stage {
     T c1, c2, c3;
 };
 
+// One problem of a batch (sine stream-function fields only): its geometry,
+// its velocity tables, where its state and stream tables live, and the wave
+// shape its tiles use (nodes per wave along x: 64, 32 or 16).
+template <typename T>
+struct BatchProb {
+    Geom g;
+    T S[4][4], SQ[4][4], SR[4][4];
+    T kx, ky;
+    int64_t off;       // element offset of this problem's phi plane in the batch state
+    int64_t tab;       // element offset of its column table (row table follows)
+    unsigned wx;       // nodes per wave along x
+    unsigned tiles_x;  // tiles per row group
+};
+
+// One tile of the flat work list: problem index and tile index within it.
+struct TileRef {
+    unsigned prob;
+    unsigned local;
+};
+
 }  // namespace gals
 
 struct gals_ctx {
@@ -77,12 +98,26 @@ struct gals_ctx {
 
 namespace gals {
 
+// Thread-local error text returned by gals_last_error() (gals_api.hip).
+void set_error_v(const char *fmt, va_list ap);
+
 // Launchers (kernels_*.hip). Each returns a hipError_t of the launch.
 hipError_t launch_step(const gals_ctx *ctx, const void *phi, const void *grad, void *phi_o,
                        void *grad_o, double dt, double c1, double c2, double c3,
                        const void *coltab, const void *rowtab, hipStream_t s);
 // Per-column / per-row stream-function tables (GALS_VEL_STREAM_SIN only).
 hipError_t launch_stream_tables(const gals_ctx *ctx, void *coltab, void *rowtab, hipStream_t s);
+
+// Batched stream-function problems (batch.hip). probs/tiles are device arrays.
+hipError_t launch_batch_tables(int prec, const void *probs_f64, int nprob, int max_entries,
+                               void *tab, hipStream_t s);
+hipError_t launch_batch_step(int prec, int mixed, const void *probs, const TileRef *tiles,
+                             unsigned ntiles, double dt, double c1, double c2, double c3,
+                             const void *tab, const void *in, void *out, unsigned blocks,
+                             hipStream_t s);
+hipError_t batch_step_blocks_per_cu(int prec, int mixed, int *blocks);
+hipError_t launch_batch_copy(int prec, const void *probs, const TileRef *tiles, unsigned ntiles,
+                             const void *in, void *out, unsigned blocks, hipStream_t s);
 hipError_t launch_eval(const gals_ctx *ctx, const void *phi, const void *grad, const double *pts,
                        int64_t npts, void *val, void *normal, void *curv, hipStream_t s);
 hipError_t launch_norms(const gals_ctx *ctx, const void *phi, const void *grad,

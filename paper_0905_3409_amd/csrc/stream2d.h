@@ -1,0 +1,218 @@
+// Sine stream-function fields in 2D, s = sum_{m,n} S[m][n] sin(m pi x) sin(n pi y):
+// per-column / per-row tables, the per-node jet and its Taylor stages, and the
+// whole GA-CIR step for one node. Shared by the single-grid and the batched
+// kernels so that both do identical per-node arithmetic.
+#pragma once
+
+#include "hermite.h"
+
+namespace gals {
+
+// The field is separable, so every derivative at a node is a short dot
+// product of a per-column and a per-row table:
+//   coltab[i][a][n] = sum_m S[m][n] (m pi)^a sin^(a)(m pi x_i)
+//   rowtab[j][b][n] = (n pi)^b sin^(b)(n pi y_j)
+//   d^a/dx^a d^b/dy^b s(x_i, y_j) = sum_n coltab[i][a][n] rowtab[j][b][n]
+// with sin^(a) = sin, cos, -sin, -cos, sin for a = 0..4. Entries are built in
+// FP64 and rounded to T. id < n[0]: column id; n[0] <= id < n[0]+n[1]: row.
+template <typename T>
+__device__ __forceinline__ void stream_table_entry(const Geom &g, const double (&S)[4][4], int id,
+                                                   T *__restrict__ coltab, T *__restrict__ rowtab)
+{
+    const int nx = g.n[0], ny = g.n[1];
+    if (id < nx) {
+        const double x = g.lo[0] + double(id) * g.h[0];
+        double s[4], c[4];
+        for (int m = 0; m < 4; m++) sincospi(double(m + 1) * x, &s[m], &c[m]);
+        for (int a = 0; a < 5; a++)
+            for (int n = 0; n < 4; n++) {
+                double u = 0.0;
+                for (int m = 0; m < 4; m++) {
+                    const double k = (m + 1) * kPi;
+                    double f = (a & 1) ? c[m] : s[m];
+                    if (a & 2) f = -f;
+                    double ka = 1.0;
+                    for (int q = 0; q < a; q++) ka *= k;
+                    u += S[m][n] * ka * f;
+                }
+                coltab[int64_t(id) * kJet + 4 * a + n] = T(u);
+            }
+    } else if (id < nx + ny) {
+        const int j = id - nx;
+        const double y = g.lo[1] + double(j) * g.h[1];
+        for (int n = 0; n < 4; n++) {
+            double s, c;
+            sincospi(double(n + 1) * y, &s, &c);
+            const double k = (n + 1) * kPi;
+            double kb = 1.0;
+            for (int b = 0; b < 5; b++) {
+                double f = (b & 1) ? c : s;
+                if (b & 2) f = -f;
+                rowtab[int64_t(j) * kJet + 4 * b + n] = T(kb * f);
+                kb *= k;
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T dot4(const T *u, const T *y)
+{
+    return u[0] * y[0] + u[1] * y[1] + u[2] * y[2] + u[3] * y[3];
+}
+
+// The 4-jet of s at a node, pre-scaled for Taylor evaluation at an offset
+// (dx, dy): degree 3 for the velocity (-s_y, s_x), degree 2 for its
+// derivatives. a.. = d../2, t.. = d../6.
+template <typename T>
+struct StreamJet {
+    T d10, d01, d20, d11, d02, d30, d21, d12, d03;
+    T a30, a12, a21, a03, a40, a31, a22, a13, a04, t40, t13, t31, t04;
+};
+
+template <typename T>
+__device__ __forceinline__ void stream_jet(const T *u, const T *y, StreamJet<T> &J)
+{
+    J.d10 = dot4(u + 4, y);
+    J.d01 = dot4(u, y + 4);
+    J.d20 = dot4(u + 8, y);
+    J.d11 = dot4(u + 4, y + 4);
+    J.d02 = dot4(u, y + 8);
+    J.d30 = dot4(u + 12, y);
+    J.d21 = dot4(u + 8, y + 4);
+    J.d12 = dot4(u + 4, y + 8);
+    J.d03 = dot4(u, y + 12);
+    const T d40 = dot4(u + 16, y), d31 = dot4(u + 12, y + 4), d22 = dot4(u + 8, y + 8);
+    const T d13 = dot4(u + 4, y + 12), d04 = dot4(u, y + 16);
+    const T half = T(0.5), sixth = T(1.0 / 6.0);
+    J.a30 = half * J.d30; J.a12 = half * J.d12; J.a21 = half * J.d21; J.a03 = half * J.d03;
+    J.a40 = half * d40; J.a31 = half * d31; J.a22 = half * d22; J.a13 = half * d13;
+    J.a04 = half * d04;
+    J.t40 = sixth * d40; J.t13 = sixth * d13; J.t31 = sixth * d31; J.t04 = sixth * d04;
+}
+
+// (s_x, s_y, s_xx, s_xy, s_yy) at offset (dx, dy) from the node, each
+// Taylor polynomial in nested (Horner) form.
+template <typename T>
+__device__ __forceinline__ void stream_taylor(const StreamJet<T> &J, T dx, T dy, T &sx, T &sy,
+                                              T &sxx, T &sxy, T &syy)
+{
+    // s_x: d10 + dx (d20 + dx (a30 + t40 dx + a31 dy)) + dy (d11 + dx (d21 + a22 dy) + dy (a12 + t13 dy))
+    sx = J.d10 + dx * (J.d20 + dx * (J.a30 + J.t40 * dx + J.a31 * dy)) +
+         dy * (J.d11 + dx * (J.d21 + J.a22 * dy) + dy * (J.a12 + J.t13 * dy));
+    // s_y: d01 + dx (d11 + dx (a21 + t31 dx + a22 dy)) + dy (d02 + dx (d12 + a13 dy) + dy (a03 + t04 dy))
+    sy = J.d01 + dx * (J.d11 + dx * (J.a21 + J.t31 * dx + J.a22 * dy)) +
+         dy * (J.d02 + dx * (J.d12 + J.a13 * dy) + dy * (J.a03 + J.t04 * dy));
+    // second derivatives, degree 2: c0 + dx (cx + cxx dx + cxy dy) + dy (cy + cyy dy)
+    sxx = J.d20 + dx * (J.d30 + J.a40 * dx + T(2) * J.a31 * dy) + dy * (J.d21 + J.a22 * dy);
+    sxy = J.d11 + dx * (J.d21 + J.a31 * dx + T(2) * J.a22 * dy) + dy * (J.d12 + J.a13 * dy);
+    syy = J.d02 + dx * (J.d12 + J.a22 * dx + T(2) * J.a13 * dy) + dy * (J.d03 + J.a04 * dy);
+}
+
+// Velocity and its Jacobian at node + (dx, dy), stage factor c: the Taylor
+// polynomial of the node's jet when its truncation stays below FP32 rounding
+// (kx |dx| + ky |dy| <= kTaylorMax), the exact modal sum otherwise (and
+// always in FP64). P carries the stream tables S, SQ, SR and kx, ky.
+template <typename T, bool TAYLOR, class P>
+__device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J, double x0,
+                                             double y0, T dx, T dy, T c, T *v, T *A)
+{
+    if (TAYLOR && p.kx * fabs(dx) + p.ky * fabs(dy) <= T(kTaylorMax)) {
+        T sx, sy, sxx, sxy, syy;
+        stream_taylor(J, dx, dy, sx, sy, sxx, sxy, syy);
+        from_stream(sx, sy, sxx, sxy, syy, c, v, A);
+    } else {
+        const double pos[2] = {x0 + double(dx), y0 + double(dy)};
+        vel_stream(p, pos, c, v, A);
+    }
+}
+
+// One GA-CIR step at node (i, j) of a grid with a sine stream-function field:
+// the node's jet from the column row U and the table row Y, the three
+// Shu-Osher stages, the superconsistent Jacobian, the FP64 foot in cell
+// units, the boundary treatment, the gather and the bicubic update.
+template <typename T, int MIX, bool TAYLOR, class P>
+__device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Stage<T> &st,
+                                            double dt, const T *__restrict__ U,
+                                            const T *__restrict__ Y, Rsrc rphi, Rsrc rgx,
+                                            Rsrc rgy, T *__restrict__ phi_o,
+                                            T *__restrict__ gx_o, T *__restrict__ gy_o, int i,
+                                            int j)
+{
+    StreamJet<T> jet;
+    {
+        T y[kJet], u[kJet];
+#pragma unroll
+        for (int k = 0; k < kJet; k++) {
+            y[k] = Y[k];
+            u[k] = U[k];
+        }
+        stream_jet(u, y, jet);
+    }
+    const double x0 = g.lo[0] + double(i) * g.h[0], y0 = g.lo[1] + double(j) * g.h[1];
+    const T dtT = T(dt);
+    // stage 1 at the node, time t + dt
+    T v0[2], A0[4];
+    from_stream(jet.d10, jet.d01, jet.d20, jet.d11, jet.d02, st.c1, v0, A0);
+    // stage 2 at x1 = x - dt v0, time t
+    T v1[2], A1[4];
+    stream_stage<T, TAYLOR>(p, jet, x0, y0, -dtT * v0[0], -dtT * v0[1], st.c2, v1, A1);
+    // stage 3 at x2 = x - dt (v0 + v1) / 4, time t + dt/2
+    T v2[2], A2[4];
+    stream_stage<T, TAYLOR>(p, jet, x0, y0, -dtT * (T(0.25) * v0[0] + T(0.25) * v1[0]),
+                            -dtT * (T(0.25) * v0[1] + T(0.25) * v1[1]), st.c3, v2, A2);
+    T J[4];
+    jacobian_chain<T, 2>(A0, A1, A2, dtT, J);
+
+    // foot in cell units, FP64: s = node - dt (v0/6 + v1/6 + 2 v2/3) / h
+    double s[2];
+    s[0] = double(i) - dt * (double(v0[0]) * (1.0 / 6.0) + double(v1[0]) * (1.0 / 6.0) +
+                             double(v2[0]) * (2.0 / 3.0)) * g.inv_h[0];
+    s[1] = double(j) - dt * (double(v0[1]) * (1.0 / 6.0) + double(v1[1]) * (1.0 / 6.0) +
+                             double(v2[1]) * (2.0 / 3.0)) * g.inv_h[1];
+    unsigned out = 0;
+    int cell[2];
+    double xi[2];
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+        if (g.bc == GALS_BC_NEUMANN) {
+            if (s[a] < 0.0) { s[a] = 0.0; out |= 1u << a; }
+            else if (s[a] > double(g.nc[a])) { s[a] = double(g.nc[a]); out |= 1u << a; }
+        }
+        // cell index clamped to [0, nc-1], local coordinate unclamped
+        const double fl = fmin(fmax(floor(s[a]), 0.0), double(g.nc[a] - 1));
+        cell[a] = int(fl);
+        xi[a] = s[a] - fl;
+    }
+
+    T d[4][4];
+    gather2d<T, MIX>(g, rphi, rgx, rgy, cell[0], cell[1], d);
+    Basis<T> bx, by;
+    basis<T, false>(T(xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
+    basis<T, false>(T(xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
+    T H, Hx, Hy;
+    hermite2d(d, bx, by, H, Hx, Hy);
+    if (out & 1u) Hx = T(0);
+    if (out & 2u) Hy = T(0);
+
+    const int64_t o = int64_t(j) * g.pitch + i;
+    phi_o[o] = H;
+    gx_o[o] = J[0] * Hx + J[2] * Hy;
+    gy_o[o] = J[1] * Hx + J[3] * Hy;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin by id, and each XCD has its
+// own L2. Give XCD x a contiguous band of tiles (walked row group by row
+// group) so the halo rows a tile gathers were just fetched into the same L2
+// by its neighbours. Returns false for ids past the last tile.
+__device__ __forceinline__ bool xcd_tile(unsigned tiles_x, unsigned tiles, unsigned &tx,
+                                         unsigned &ty)
+{
+    const unsigned per = (tiles + 7u) / 8u;
+    const unsigned t = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+    tx = t % tiles_x;
+    ty = t / tiles_x;
+    return t < tiles;
+}
+
+}  // namespace gals

@@ -66,8 +66,9 @@ __device__ __forceinline__ void vel_affine(const Vel<T> &p, const double *x, int
 }
 
 // Stream function s = sum_{m,n} S[m][n] sin((m+1) pi x) sin((n+1) pi y).
-template <typename T>
-__device__ __forceinline__ void vel_stream(const Vel<T> &p, const double *x, T c, T *v, T *J)
+// Params is any parameter block with the tables S, SQ, SR.
+template <typename T, class Params>
+__device__ __forceinline__ void vel_stream(const Params &p, const double *x, T c, T *v, T *J)
 {
     T sx[4], cx[4], sy[4], cy[4];
     sincos_multiples(T(x[0]), sx, cx);

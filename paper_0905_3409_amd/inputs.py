@@ -213,6 +213,30 @@ def vecpot_spheres(seed=2, n=256, steps=512, cfl=0.9, period=3.0, nspheres=8,
                      phi, psi, seed=seed, cfl=cfl, centres=centres, radii=radii)
 
 
+def batched_stream_circles(seed=4, nprob=512, steps=256, cfl=0.8, period=2.0,
+                           log2_min=5.0, log2_max=9.0, sizes=None):
+    """Many independent unit-square problems: cells per side
+    round(2^U(log2_min, log2_max)) (32^2 .. 512^2 by default; ``sizes``, a
+    list of (nx, ny), overrides the draw), each with its own 4-circle union and
+    its own 8-mode sine stream function scaled so that the largest node speed
+    at t = 0 is cfl * h / dt, h the smaller cell side, dt = period / steps."""
+    rng = np.random.default_rng(seed)
+    if sizes is None:
+        sides = np.rint(2.0 ** rng.uniform(log2_min, log2_max, nprob)).astype(int)
+        sizes = [(int(n), int(n)) for n in sides]
+    dt = period / steps
+    probs = []
+    for nx, ny in sizes:
+        ncell = (int(nx), int(ny))
+        centres = rng.uniform(0.2, 0.8, (4, 2))
+        radii = rng.uniform(0.05, 0.15, 4)
+        params = stream_modes(rng, 8, ncell, cfl * (1.0 / max(ncell)) / dt)
+        phi, psi = sdf_union(node_grid(ncell), centres, radii)
+        probs.append(dict(ncell=ncell, params=params, phi0=phi, psi0=psi))
+    return dict(name="batched_stream_circles", kind=STREAM_SIN, period=float(period),
+                dt=float(dt), steps=int(steps), t0=0.0, problems=probs, seed=seed, cfl=cfl)
+
+
 def random_points(seed, npts, dim, lo=0.0, hi=1.0):
     """npts uniform points, shape (npts, dim)."""
     rng = np.random.default_rng(seed)

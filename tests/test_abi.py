@@ -156,3 +156,123 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pkg, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         pkg.lib()
+
+
+def _batch(ncells, prec=pkg.F32, mixed=pkg.MIXED_CENTRAL, bc=pkg.BC_NEUMANN, device=-1, lo=None,
+           hi=None):
+    L = pkg.lib()
+    n = len(ncells)
+    b = ctypes.c_void_p()
+    nc = (ctypes.c_int64 * (2 * n))(*[v for c in ncells for v in c])
+    lo = (ctypes.c_double * (2 * n))(*(lo if lo is not None else [0.0] * (2 * n)))
+    hi = (ctypes.c_double * (2 * n))(*(hi if hi is not None else [1.0] * (2 * n)))
+    rc = L.gals_batch_create(ctypes.byref(b), n, nc, lo, hi, prec, mixed, bc, device)
+    return rc, b
+
+
+def test_batch_create_validation():
+    L = pkg.lib()
+    b = ctypes.c_void_p()
+    nc = (ctypes.c_int64 * 2)(8, 8)
+    lo = (ctypes.c_double * 2)(0.0, 0.0)
+    hi = (ctypes.c_double * 2)(1.0, 1.0)
+    assert L.gals_batch_create(ctypes.byref(b), 0, nc, lo, hi, pkg.F32, 0, 0, -1) == pkg.EINVAL
+    assert L.gals_batch_create(None, 1, nc, lo, hi, pkg.F32, 0, 0, -1) == pkg.EINVAL
+    assert L.gals_batch_create(ctypes.byref(b), 65536, nc, lo, hi, pkg.F32, 0, 0, -1) == pkg.EINVAL
+    assert _batch([(8, 8), (1, 8)])[0] == pkg.EINVAL
+    assert b"problem 1 axis 0" in L.gals_last_error()
+    assert _batch([(8, 8)], prec=5)[0] == pkg.EINVAL
+    assert _batch([(8, 8)], mixed=1)[0] == pkg.EINVAL
+    assert _batch([(8, 8)], bc=3)[0] == pkg.EINVAL
+    assert _batch([(8, 8)], device=-3)[0] == pkg.EINVAL
+    assert _batch([(8, 8)], lo=[0.0, 1.0], hi=[1.0, 1.0])[0] == pkg.EINVAL
+    assert _batch([(40000, 20000)])[0] == pkg.EINVAL  # plane of 2 GiB or more
+    rc, b = _batch([(8, 8), (30, 70)], bc=pkg.BC_EXTRAPOLATE)
+    assert rc == pkg.OK
+    assert L.gals_batch_destroy(b) == pkg.OK
+    assert L.gals_batch_destroy(None) == pkg.OK
+
+
+def test_batch_layout_and_workspace():
+    L = pkg.lib()
+    ncells = [(8, 8), (33, 47), (100, 3), (511, 512)]
+    for prec, es in ((pkg.F32, 4), (pkg.F64, 8)):
+        rc, b = _batch(ncells, prec=prec)
+        assert rc == pkg.OK
+        n = len(ncells)
+        off, pitch, plane = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)()
+        total = ctypes.c_int64()
+        assert L.gals_batch_layout(b, off, pitch, plane, ctypes.byref(total)) == pkg.OK
+        o = 0
+        for p, (nx, ny) in enumerate(ncells):
+            assert off[p] == o
+            assert pitch[p] % 64 == 0 and nx + 1 <= pitch[p] < nx + 65
+            assert plane[p] == pitch[p] * (ny + 1)
+            o += 3 * plane[p]
+        assert total.value == o
+        ws = ctypes.c_size_t()
+        assert L.gals_batch_workspace_bytes(b, ctypes.byref(ws)) == pkg.OK
+        tables = sum(nx + ny + 2 for nx, ny in ncells) * 20 * es
+        assert total.value * es + tables <= ws.value <= total.value * es + tables + 256 * (n * 64 + 2)
+        L.gals_batch_destroy(b)
+
+
+def test_batch_velocity_tiles_and_advance_validation():
+    L = pkg.lib()
+    rc, b = _batch([(8, 8), (40, 20)])
+    assert rc == pkg.OK
+    P = ctypes.POINTER(ctypes.c_double)
+    good = np.array([0.01, 1, 2, -0.02, 4, 4], dtype=np.float64)
+    assert L.gals_batch_set_velocity(b, 0, pkg.STREAM_SIN, good.ctypes.data_as(P), 6, 2.0) == pkg.OK
+    assert L.gals_batch_set_velocity(b, 2, pkg.STREAM_SIN, good.ctypes.data_as(P), 6, 2.0) == pkg.EINVAL
+    assert L.gals_batch_set_velocity(b, 1, pkg.AFFINE, good.ctypes.data_as(P), 6, 2.0) == pkg.ENOTSUP
+    assert L.gals_batch_set_velocity(b, 1, pkg.STREAM_SIN, good.ctypes.data_as(P), 5, 2.0) == pkg.EINVAL
+    bad = np.array([0.01, 5, 1], dtype=np.float64)
+    assert L.gals_batch_set_velocity(b, 1, pkg.STREAM_SIN, bad.ctypes.data_as(P), 3, 2.0) == pkg.ENOTSUP
+    bad = np.array([np.nan, 1, 1], dtype=np.float64)
+    assert L.gals_batch_set_velocity(b, 1, pkg.STREAM_SIN, bad.ctypes.data_as(P), 3, 2.0) == pkg.EINVAL
+    # one period for the whole batch
+    assert L.gals_batch_set_velocity(b, 1, pkg.STREAM_SIN, good.ctypes.data_as(P), 6, 3.0) == pkg.EINVAL
+    assert b"one period" in L.gals_last_error()
+    tiles = (ctypes.c_int * 4)(64, 32, 16, 16)
+    assert L.gals_batch_set_tiles(b, tiles) == pkg.OK
+    got = (ctypes.c_int * 4)()
+    assert L.gals_batch_get_tiles(b, got) == pkg.OK and list(got) == [64, 32, 16, 16]
+    assert L.gals_batch_set_tiles(b, (ctypes.c_int * 4)(64, 8, 16, 16)) == pkg.EINVAL
+    assert L.gals_batch_get_tiles(b, got) == pkg.OK and list(got) == [64, 32, 16, 16]
+    ws_bytes = ctypes.c_size_t()
+    L.gals_batch_workspace_bytes(b, ctypes.byref(ws_bytes))
+    state, ws = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 40)
+    # problem 1 has no velocity yet
+    assert L.gals_batch_advance(b, state, 0.0, 0.01, 1, 0, ws, ws_bytes.value, None) == pkg.EINVAL
+    assert b"problem 1" in L.gals_last_error()
+    assert L.gals_batch_set_velocity(b, 1, pkg.STREAM_SIN, good.ctypes.data_as(P), 6, 2.0) == pkg.OK
+    args = dict(t0=0.0, dt=0.01, steps=1, ws=ws, wsb=ws_bytes.value)
+
+    def adv(**kw):
+        a = dict(args, **kw)
+        return L.gals_batch_advance(b, state, a["t0"], a["dt"], a["steps"], 0, a["ws"], a["wsb"],
+                                    None)
+
+    assert adv(dt=0.0) == pkg.EINVAL
+    assert adv(dt=float("inf")) == pkg.EINVAL
+    assert adv(t0=float("nan")) == pkg.EINVAL
+    assert adv(steps=-1) == pkg.EINVAL
+    assert adv(wsb=ws_bytes.value - 1) == pkg.EINVAL
+    assert adv(ws=ctypes.c_void_p((1 << 40) + 4)) == pkg.EINVAL  # workspace not 256-aligned
+    assert adv(ws=ctypes.c_void_p((1 << 20) + 256)) == pkg.EINVAL  # overlaps the state
+    assert adv(steps=0) == pkg.OK  # nothing to do, nothing touched
+    assert adv() == pkg.EINVAL  # host-only batch cannot launch
+    assert b"host-only" in L.gals_last_error()
+    best = ctypes.c_double()
+    assert L.gals_batch_autotune(b, state, 0.01, 0, ws, ws_bytes.value, None,
+                                 ctypes.byref(best)) == pkg.EINVAL
+    L.gals_batch_destroy(b)
+
+
+def test_batch_binding_layout_roundtrip():
+    """The Python views of each problem's planes address the documented layout."""
+    bt = pkg.Batch([(8, 8), (33, 5), (70, 70)], device=-1)
+    assert bt.nprob == 3 and bt.num_nodes() == 81 + 34 * 6 + 71 * 71
+    assert list(bt.offset) == [0, 3 * bt.plane[0], 3 * (bt.plane[0] + bt.plane[1])]
+    assert bt.total_elems == 3 * int(bt.plane.sum())

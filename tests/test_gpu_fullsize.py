@@ -130,3 +130,40 @@ def test_c2_full_run_fp32_tracks_fp64_and_returns(c2):
     dn = g64.norms(s64, ref, 1.5 * h, 3 * h)
     assert np.allclose(dn, n64, rtol=1e-12, atol=1e-300)
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_c3_curvature_at_a_million_points(c3, dtype):
+    """Point evaluation at 1e6 seeded points on the 257^3 grid: a sample of
+    3000 against the oracle, and near each sphere the curvature of the signed
+    distance is 2/|x - c| (sum of principal curvatures)."""
+    import torch
+    w = c3
+    g = pkg.Grid(w["ncell"], w["lo"], w["hi"], dtype=dtype)
+    st = g.from_numpy(w["phi0"], w["psi0"])
+    pts = inputs.random_points(7, 1_000_000, 3)
+    val, nrm, cur = g.eval_points(st, pts)
+    torch.cuda.synchronize()
+    val = val.double().cpu().numpy()
+    cur = cur.double().cpu().numpy()
+    phi, psi = g.to_numpy(st)
+    del st
+    idx = np.random.default_rng(1).integers(0, len(pts), 3000)
+    o = oracle.eval_points(3, w["ncell"], w["lo"], w["hi"], phi, psi, pts[idx])
+    if dtype == "float64":
+        assert rel(val[idx], o["val"]) <= TOL64
+    else:
+        assert rel(val[idx], o["val"]) <= 64 * 2.0 ** -24
+    # curvature of the union's signed distance near sphere k, away from the
+    # other spheres and from the centre: kappa = 2 / r
+    c, r = w["centres"], w["radii"]
+    dist = np.linalg.norm(pts[:, None, :] - c[None, :, :], axis=2) - r[None, :]
+    k = np.argmin(dist, axis=1)
+    d = dist[np.arange(len(pts)), k]
+    second = np.sort(dist, axis=1)[:, 1]
+    near = (np.abs(d) < 0.5 * r[k]) & (second - d > 0.05)
+    rr = np.linalg.norm(pts[near] - c[k[near]], axis=1)
+    err = np.abs(cur[near] - 2.0 / rr) / (2.0 / rr)
+    print(f"{dtype}: {near.sum()} points near a sphere, median rel kappa err {np.median(err):.2e}")
+    assert near.sum() > 10000
+    assert np.median(err) < 0.02
