@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", choices=["single", "batched"], default="single")
+    ap.add_argument("--tiles", default="",
+                    help="batched only: wave widths per size class, e.g. 64,0,16,64, "
+                         "instead of the autotuner's choice")
     ap.add_argument("--profile", action="store_true",
                     help="short FP32 advance plus a plain device copy of known size "
                          "(for calibrating rocprofv3 byte counters); prints no JSON")
@@ -249,6 +252,16 @@ def bench_batched(args):
     st = ref.clone()
     s = torch.cuda.Stream()
     if args.profile:
+        # the shapes the timed run would use, then a short advance
+        if args.tiles:
+            b.set_tiles([int(v) for v in args.tiles.split(",")])
+        else:
+            scratch = ref.clone()
+            b.autotune(scratch, w["dt"], steps=8)
+            del scratch
+        torch.cuda.synchronize()
+        log(f"profile: wave widths per class {b.get_tiles()}; the last "
+            f"{args.inner or 16} step launches are the measured ones")
         b.advance(st, 0.0, w["dt"], args.inner or 16)
         nbytes = 256 << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
@@ -256,10 +269,14 @@ def bench_batched(args):
         torch.cuda.synchronize()
         log(f"profile: batched FP32 steps on {nodes} nodes, then a {nbytes} B device copy")
         return 0
-    scratch = ref.clone()
-    tune_ms = b.autotune(scratch, w["dt"], steps=8)
-    del scratch
-    log(f"autotune: wave widths per class {b.get_tiles()}, {tune_ms:.3f} ms for 8 steps")
+    if args.tiles:
+        b.set_tiles([int(v) for v in args.tiles.split(",")])
+        log(f"wave widths per class {b.get_tiles()} (given)")
+    else:
+        scratch = ref.clone()
+        tune_ms = b.autotune(scratch, w["dt"], steps=8)
+        del scratch
+        log(f"autotune: wave widths per class {b.get_tiles()}, {tune_ms:.3f} ms for 8 steps")
 
     def bench_step(ev=None):
         with torch.cuda.stream(s):
@@ -321,7 +338,9 @@ def bench_batched(args):
                                "side, 4 circles and an 8-mode sine stream function each, "
                                "256 steps of dt 2/256, CFL 0.8",
                    "grids": len(probs), "nodes": nodes, "time_steps_per_step": inner,
-                   "wave_widths_per_class": b.get_tiles(), "graph": True, "seed": w["seed"]},
+                   "wave_widths_per_class": b.get_tiles(),
+                   "wave_widths_from": "given" if args.tiles else "autotuner",
+                   "graph": True, "seed": w["seed"]},
         "hbm_gbps_algorithmic": gbps,
         "roofline": roofline,
         "cpu_baseline": cpu,

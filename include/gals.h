@@ -199,7 +199,9 @@ int gals_batch_workspace_bytes(const gals_batch *b, size_t *bytes);
 int gals_batch_set_velocity(gals_batch *b, int64_t p, int kind, const double *params,
                             int64_t nparams, double period);
 /* Wave shape per grid-size class (nodes per row <= 48, <= 96, <= 192, more):
- * nodes per wave along x, 64, 32 or 16 (a wave covers 64/w rows). */
+ * nodes per wave along x, 64, 32 or 16 (a wave covers 64/w rows), or 0 for
+ * the row-major shape (a wave takes 64 consecutive nodes of the grid in
+ * row-major order). A tile is 4 waves. Default 64 for every class. */
 int gals_batch_set_tiles(gals_batch *b, const int *wave_width_per_class);
 int gals_batch_get_tiles(const gals_batch *b, int *wave_width_per_class);
 /* Advance every problem by `steps` steps (as gals_advance). use_graph != 0

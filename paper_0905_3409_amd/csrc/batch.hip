@@ -1,9 +1,12 @@
 // Many independent 2D grids with sine stream-function fields advanced by one
 // persistent launch per step. The work list is a flat array of tiles over all
-// problems; XCD x owns a contiguous band of it (so halo rows stay in its L2)
-// and the blocks on that XCD stride through the band. A tile is 4 waves; a
-// wave covers WX x (64/WX) nodes with WX = 64, 32 or 16 chosen per problem,
-// so narrow grids do not leave most lanes idle. Per-node arithmetic is the
+// problems; XCD x owns a contiguous band of it (so the halo rows a tile
+// gathers were just fetched into the same L2 by its neighbours) and the
+// blocks on that XCD stride through the band. (Per-tile atomic queues were
+// measured as well: no faster, the tiles are even enough.)
+// A tile is 4 waves. A wave covers WX x (64/WX) nodes with WX = 64, 32 or 16,
+// or, in the row-major shape, 64 consecutive nodes of the grid in row-major
+// order (no lanes lost to a ragged row end). Per-node arithmetic is the
 // single-grid kernel's (stream_node), so batched and single runs agree bit
 // for bit.
 #include "stream2d.h"
@@ -22,19 +25,44 @@ __global__ __launch_bounds__(kBlock) void k_batch_tables(const BatchProb<double>
     stream_table_entry(P.g, P.S, id, col, row);
 }
 
+// Node (i, j) of lane `lane` in wave `wave` of tile `local`; false if the
+// lane has no node.
+template <unsigned WX, class P>
+__device__ __forceinline__ bool tile_node(const P &p, unsigned local, unsigned wave,
+                                          unsigned lane, int &i, int &j)
+{
+    const Geom &g = p.g;
+    if constexpr (WX == 0u) {
+        // row-major: node k = j n0 + i; j from an FP32 estimate of k / n0
+        // corrected once (the estimate is off by less than one for every
+        // k < 2^31 with j < 2^20)
+        const unsigned k = local * 256u + wave * 64u + lane;
+        if (k >= unsigned(g.nodes)) return false;
+        int jj = int(float(k) * p.inv_n0);
+        int ii = int(k) - jj * g.n[0];
+        if (ii < 0) { jj--; ii += g.n[0]; }
+        else if (ii >= g.n[0]) { jj++; ii -= g.n[0]; }
+        i = ii;
+        j = jj;
+        return true;
+    } else {
+        constexpr unsigned WY = 64u / WX;  // rows per wave
+        const unsigned tx = local % p.tiles_x, ty = local / p.tiles_x;
+        i = int(tx * WX + lane % WX);
+        j = int(ty * 4u * WY + wave * WY + lane / WX);
+        if constexpr (WY == 1) j = __builtin_amdgcn_readfirstlane(j);
+        return j < g.n[1] && i < g.n[0];
+    }
+}
+
 template <typename T, int MIX, bool TAYLOR, unsigned WX>
 __device__ __forceinline__ void batch_tile(const BatchProb<T> &P, unsigned local, const Stage<T> &st,
                                            double dt, const T *__restrict__ tab,
                                            const T *__restrict__ in, T *__restrict__ out)
 {
-    constexpr unsigned WY = 64u / WX;  // rows per wave
-    const unsigned tx = local % P.tiles_x, ty = local / P.tiles_x;
-    const unsigned lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    const int i = int(tx * WX + lane % WX);
-    int j = int(ty * 4u * WY + wave * WY + lane / WX);
-    if constexpr (WY == 1) j = __builtin_amdgcn_readfirstlane(j);
+    int i, j;
+    if (!tile_node<WX>(P, local, threadIdx.x >> 6, threadIdx.x & 63u, i, j)) return;
     const Geom &g = P.g;
-    if (j >= g.n[1] || i >= g.n[0]) return;
     const T *col = tab + P.tab;
     const T *row = col + int64_t(g.n[0]) * kJet;
     const T *phi = in + P.off;
@@ -64,8 +92,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchProb<T> *__res
             batch_tile<T, MIX, TAYLOR, 64u>(P, tr.local, st, dt, tab, in, out);
         else if (P.wx == 32u)
             batch_tile<T, MIX, TAYLOR, 32u>(P, tr.local, st, dt, tab, in, out);
-        else
+        else if (P.wx == 16u)
             batch_tile<T, MIX, TAYLOR, 16u>(P, tr.local, st, dt, tab, in, out);
+        else
+            batch_tile<T, MIX, TAYLOR, 0u>(P, tr.local, st, dt, tab, in, out);
     }
 }
 
@@ -74,12 +104,8 @@ template <typename T, unsigned WX>
 __device__ __forceinline__ void copy_tile(const BatchProb<T> &P, unsigned local,
                                           const T *__restrict__ in, T *__restrict__ out)
 {
-    constexpr unsigned WY = 64u / WX;
-    const unsigned tx = local % P.tiles_x, ty = local / P.tiles_x;
-    const unsigned lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    const int i = int(tx * WX + lane % WX);
-    const int j = int(ty * 4u * WY + wave * WY + lane / WX);
-    if (j >= P.g.n[1] || i >= P.g.n[0]) return;
+    int i, j;
+    if (!tile_node<WX>(P, local, threadIdx.x >> 6, threadIdx.x & 63u, i, j)) return;
     const int64_t o = P.off + int64_t(j) * P.g.pitch + i;
     out[o] = in[o];
     out[o + P.g.plane] = in[o + P.g.plane];
@@ -97,7 +123,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_copy(const BatchProb<T> *__res
         const BatchProb<T> &P = probs[tr.prob];
         if (P.wx == 64u) copy_tile<T, 64u>(P, tr.local, in, out);
         else if (P.wx == 32u) copy_tile<T, 32u>(P, tr.local, in, out);
-        else copy_tile<T, 16u>(P, tr.local, in, out);
+        else if (P.wx == 16u) copy_tile<T, 16u>(P, tr.local, in, out);
+        else copy_tile<T, 0u>(P, tr.local, in, out);
     }
 }
 
@@ -121,47 +148,20 @@ hipError_t launch_batch_step(int prec, int mixed, const void *probs, const TileR
 {
     if (prec == GALS_F32) {
         const Stage<float> st{float(c1), float(c2), float(c3)};
-        if (mixed == GALS_MIXED_ZERO)
-            hipLaunchKernelGGL((k_batch_step<float, GALS_MIXED_ZERO, true>), dim3(blocks),
-                               dim3(kBlock), 0, s, (const BatchProb<float> *)probs, tiles, ntiles,
-                               st, dt, (const float *)tab, (const float *)in, (float *)out);
-        else
-            hipLaunchKernelGGL((k_batch_step<float, GALS_MIXED_CENTRAL, true>), dim3(blocks),
-                               dim3(kBlock), 0, s, (const BatchProb<float> *)probs, tiles, ntiles,
-                               st, dt, (const float *)tab, (const float *)in, (float *)out);
+        auto kern = mixed == GALS_MIXED_ZERO ? k_batch_step<float, GALS_MIXED_ZERO, true>
+                                             : k_batch_step<float, GALS_MIXED_CENTRAL, true>;
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s,
+                           (const BatchProb<float> *)probs, tiles, ntiles, st, dt,
+                           (const float *)tab, (const float *)in, (float *)out);
     } else {
         const Stage<double> st{c1, c2, c3};
-        if (mixed == GALS_MIXED_ZERO)
-            hipLaunchKernelGGL((k_batch_step<double, GALS_MIXED_ZERO, false>), dim3(blocks),
-                               dim3(kBlock), 0, s, (const BatchProb<double> *)probs, tiles,
-                               ntiles, st, dt, (const double *)tab, (const double *)in,
-                               (double *)out);
-        else
-            hipLaunchKernelGGL((k_batch_step<double, GALS_MIXED_CENTRAL, false>), dim3(blocks),
-                               dim3(kBlock), 0, s, (const BatchProb<double> *)probs, tiles,
-                               ntiles, st, dt, (const double *)tab, (const double *)in,
-                               (double *)out);
+        auto kern = mixed == GALS_MIXED_ZERO ? k_batch_step<double, GALS_MIXED_ZERO, false>
+                                             : k_batch_step<double, GALS_MIXED_CENTRAL, false>;
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s,
+                           (const BatchProb<double> *)probs, tiles, ntiles, st, dt,
+                           (const double *)tab, (const double *)in, (double *)out);
     }
     return hipGetLastError();
-}
-
-// Blocks of the step kernel that fit on one CU at once (its register use
-// decides); the persistent grid is sized to exactly that so every block is
-// resident from the start and the static tile shares finish together.
-hipError_t batch_step_blocks_per_cu(int prec, int mixed, int *blocks)
-{
-    *blocks = 0;
-    if (prec == GALS_F32)
-        return mixed == GALS_MIXED_ZERO
-                   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                         blocks, k_batch_step<float, GALS_MIXED_ZERO, true>, kBlock, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                         blocks, k_batch_step<float, GALS_MIXED_CENTRAL, true>, kBlock, 0);
-    return mixed == GALS_MIXED_ZERO
-               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                     blocks, k_batch_step<double, GALS_MIXED_ZERO, false>, kBlock, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                     blocks, k_batch_step<double, GALS_MIXED_CENTRAL, false>, kBlock, 0);
 }
 
 hipError_t launch_batch_copy(int prec, const void *probs, const TileRef *tiles, unsigned ntiles,

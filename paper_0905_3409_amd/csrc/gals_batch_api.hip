@@ -32,7 +32,8 @@ int bhip(hipError_t e, const char *what)
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-const unsigned kShapes[3] = {64u, 32u, 16u};
+// wave shapes: nodes per wave along x (a wave covers 64/w rows), 0 = row-major
+const unsigned kShapes[4] = {64u, 32u, 16u, 0u};
 
 // Grid-size class of a problem by nodes per row.
 int size_class(int n0) { return n0 <= 48 ? 0 : n0 <= 96 ? 1 : n0 <= 192 ? 2 : 3; }
@@ -69,10 +70,11 @@ namespace {
 
 size_t es(const gals_batch *b) { return b->prec == GALS_F32 ? 4 : 8; }
 
+// workspace: [ping-pong state copy | stream tables]
+int64_t tab_offset(const gals_batch *b) { return round_up(b->total_elems * int64_t(es(b)), 256); }
 size_t ws_bytes(const gals_batch *b)
 {
-    return size_t(round_up(b->total_elems * int64_t(es(b)), 256) +
-                  round_up(b->tab_elems * int64_t(es(b)), 256));
+    return size_t(tab_offset(b) + round_up(b->tab_elems * int64_t(es(b)), 256));
 }
 
 void drop_graph(gals_batch *b)
@@ -117,7 +119,16 @@ void fill_prob(const gals_batch *b, int p, BatchProb<T> &P)
     P.off = b->off[p];
     P.tab = b->tab[p];
     P.wx = b->class_wx[size_class(P.g.n[0])];
-    P.tiles_x = (unsigned(P.g.n[0]) + P.wx - 1u) / P.wx;
+    P.tiles_x = P.wx ? (unsigned(P.g.n[0]) + P.wx - 1u) / P.wx : 0u;
+    P.inv_n0 = 1.0f / float(P.g.n[0]);
+}
+
+// Tiles of problem P (4 waves of 64 lanes each).
+unsigned tile_count(const BatchProb<double> &P)
+{
+    if (P.wx == 0u) return unsigned((P.g.nodes + 255) / 256);
+    const unsigned rows = 4u * (64u / P.wx);
+    return P.tiles_x * ((unsigned(P.g.n[1]) + rows - 1u) / rows);
 }
 
 // Upload descriptors and the tile list (synchronous; never inside a capture).
@@ -133,8 +144,7 @@ int upload(gals_batch *b)
     for (int p = 0; p < b->nprob; p++) {
         fill_prob(b, p, pd[p]);
         if (b->prec == GALS_F32) fill_prob(b, p, pf[p]);
-        const unsigned wx = pd[p].wx, rows = 4u * (64u / wx);
-        const unsigned nt = pd[p].tiles_x * ((unsigned(pd[p].g.n[1]) + rows - 1u) / rows);
+        const unsigned nt = tile_count(pd[p]);
         if (uint64_t(tiles.size()) + nt > (uint64_t(1) << 31))
             return bfail(GALS_EINVAL, "gals_batch: more than 2^31 tiles in one batch");
         for (unsigned t = 0; t < nt; t++) tiles.push_back(TileRef{unsigned(p), t});
@@ -170,7 +180,7 @@ hipError_t enqueue(gals_batch *b, void *state, void *ws, double t0, double dt, i
 {
     char *w = (char *)ws;
     void *copy = w;
-    void *tab = w + round_up(b->total_elems * int64_t(es(b)), 256);
+    void *tab = w + tab_offset(b);
     hipError_t e = launch_batch_tables(b->prec, b->d_probs64, b->nprob, b->max_entries, tab, s);
     if (e != hipSuccess) return e;
     void *bufs[2] = {state, copy};
@@ -298,23 +308,18 @@ int gals_batch_create(gals_batch **out, int64_t nprob, const int64_t *ncell, con
     b->total_elems = offs;
     b->tab_elems = tabs;
     if (device >= 0) {
-        int count = 0, cus = 0, per_cu = 0;
+        int count = 0, cus = 0;
         hipError_t e = hipGetDeviceCount(&count);
         if (e == hipSuccess && (device >= count)) e = hipErrorInvalidDevice;
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-        if (e == hipSuccess) {
-            DevGuard dg(device);
-            e = dg.err;
-            if (e == hipSuccess) e = batch_step_blocks_per_cu(prec, mixed_mode, &per_cu);
-        }
         if (e != hipSuccess) {
             delete b;
             return bhip(e, "gals_batch_create: device query");
         }
-        // all blocks resident at once; a multiple of the 8 XCDs
-        per_cu = per_cu < 1 ? 1 : per_cu > 8 ? 8 : per_cu;
-        b->blocks = (unsigned(cus) * unsigned(per_cu)) / 8u * 8u;
-        if (b->blocks < 8u) b->blocks = 8u;
+        // 8 blocks of 256 threads per CU (7 are resident at the step kernel's
+        // register use; the eighth starts as others finish), a multiple of
+        // the 8 XCDs
+        b->blocks = (unsigned(cus) * 8u + 7u) / 8u * 8u;
     } else if (device != -1) {
         delete b;
         return bfail(GALS_EINVAL, "gals_batch_create: device %d", device);
@@ -391,8 +396,8 @@ int gals_batch_set_tiles(gals_batch *b, const int *wave_width_per_class)
     if (!b || !wave_width_per_class) return bfail(GALS_EINVAL, "gals_batch_set_tiles: NULL argument");
     for (int c = 0; c < 4; c++) {
         const int w = wave_width_per_class[c];
-        if (w != 64 && w != 32 && w != 16)
-            return bfail(GALS_EINVAL, "gals_batch_set_tiles: wave width must be 64, 32 or 16");
+        if (w != 64 && w != 32 && w != 16 && w != 0)
+            return bfail(GALS_EINVAL, "gals_batch_set_tiles: wave width must be 64, 32, 16 or 0");
     }
     for (int c = 0; c < 4; c++) b->class_wx[c] = unsigned(wave_width_per_class[c]);
     b->dirty = true;

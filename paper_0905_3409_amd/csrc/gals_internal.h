@@ -71,9 +71,11 @@ struct BatchProb {
     T kx, ky;
     int64_t off;       // element offset of this problem's phi plane in the batch state
     int64_t tab;       // element offset of its column table (row table follows)
-    unsigned wx;       // nodes per wave along x
-    unsigned tiles_x;  // tiles per row group
+    unsigned wx;       // nodes per wave along x; 0: row-major (64 consecutive nodes per wave)
+    unsigned tiles_x;  // tiles per row group (rectangular shapes)
+    float inv_n0;      // 1 / nodes per row (row-major shape)
 };
+
 
 // One tile of the flat work list: problem index and tile index within it.
 struct TileRef {
@@ -115,7 +117,6 @@ hipError_t launch_batch_step(int prec, int mixed, const void *probs, const TileR
                              unsigned ntiles, double dt, double c1, double c2, double c3,
                              const void *tab, const void *in, void *out, unsigned blocks,
                              hipStream_t s);
-hipError_t batch_step_blocks_per_cu(int prec, int mixed, int *blocks);
 hipError_t launch_batch_copy(int prec, const void *probs, const TileRef *tiles, unsigned ntiles,
                              const void *in, void *out, unsigned blocks, hipStream_t s);
 hipError_t launch_eval(const gals_ctx *ctx, const void *phi, const void *grad, const double *pts,

@@ -240,6 +240,8 @@ def test_batch_velocity_tiles_and_advance_validation():
     assert L.gals_batch_get_tiles(b, got) == pkg.OK and list(got) == [64, 32, 16, 16]
     assert L.gals_batch_set_tiles(b, (ctypes.c_int * 4)(64, 8, 16, 16)) == pkg.EINVAL
     assert L.gals_batch_get_tiles(b, got) == pkg.OK and list(got) == [64, 32, 16, 16]
+    assert L.gals_batch_set_tiles(b, (ctypes.c_int * 4)(0, 0, 16, 0)) == pkg.OK  # row-major
+    assert L.gals_batch_get_tiles(b, got) == pkg.OK and list(got) == [0, 0, 16, 0]
     ws_bytes = ctypes.c_size_t()
     L.gals_batch_workspace_bytes(b, ctypes.byref(ws_bytes))
     state, ws = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 40)
