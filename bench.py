@@ -38,9 +38,10 @@ HBM_PEAK_GBPS = 8000.0
 # build does not emit.)
 VALU_F32_PEAK_TFLOPS = 78.6
 # Floating-point operations per node of the FP32 stream-function step as
-# formulated (jet + Taylor stages + Jacobian chain + FP64 foot + bicubic
-# value/gradient); FMA = 2. Breakdown in the design notes.
-ALG_FLOPS_PER_NODE = 523
+# formulated, FMA = 2: jet 111, stage 1 6, stage 2 80, stage 3 86, Jacobian
+# chain 80, FP64 foot and split 18, cross derivatives 8, Hermite weights 40,
+# bicubic value and gradient 80, gradient update 6.
+ALG_FLOPS_PER_NODE = 515
 BYTES_PER_NODE = 24  # FP32 state: 3 planes read once + 3 planes written once
 
 
