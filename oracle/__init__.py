@@ -14,7 +14,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "gals_oracle.c")
+_SRCS = [os.path.join(_HERE, "gals_oracle.c"), os.path.join(_HERE, "gals_oracle_cs.c")]
 _LIB_PATH = os.path.join(_HERE, "libgals_oracle.so")
 
 # Velocity kinds (same numbering as the GPU library's public header; each side
@@ -29,7 +29,7 @@ _lib = None
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (OpenMP, no FMA contraction)."""
     cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fPIC",
-           "-shared", "-Wall", "-Wextra", "-o", _LIB_PATH, _SRC, "-lm"]
+           "-shared", "-Wall", "-Wextra", "-o", _LIB_PATH, *_SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -57,6 +57,7 @@ def _load():
     lib.orc_norms.argtypes = [i, L, D, D, D, D, D, D, d, d, D]
     lib.orc_max_speed.argtypes = [i, L, D, D, i, D, l, d, d]
     lib.orc_max_speed.restype = d
+    lib.orc_grad_cs.argtypes = [L, D, D, D, l, d, i, i, D, D, d, d, l, D, D, d, D, D]
     lib.orc_num_threads.argtypes = []
     _lib = lib
     return lib
@@ -200,3 +201,23 @@ def max_speed(dim, ncell, lo, hi, kind, params, period, t):
     if r < 0:
         raise ValueError("oracle max_speed rejected its arguments")
     return r
+
+
+def grad_cs(ncell, lo, hi, params, period, phi0, psi0, t0, dt, steps, lam=None,
+            phi_target=None, eps=0.0, mixed_mode=MIXED_CENTRAL, bc=BC_NEUMANN):
+    """Complex-step derivatives of a functional of the final 2D state with
+    respect to the folded sine stream-function table S[m][n] (returned as a
+    4 x 4 array, [m-1][n-1]). lam (3 N values: weights of phi, psi_x, psi_y)
+    selects the linear functional sum(lam . u_T); otherwise the loss
+    prod(h) sum (H_eps(phi_T) - H_eps(phi_target))^2. Returns (value, grad)."""
+    nc, lo, hi, ncp = _geom(ncell, lo, hi)
+    p, npar = _params(params)
+    phi0, psi0 = _f64(phi0), _f64(psi0)
+    lam = None if lam is None else _f64(lam)
+    tgt = None if phi_target is None else _f64(phi_target)
+    grad = np.zeros(16)
+    val = ctypes.c_double()
+    _check(_load().orc_grad_cs(ncp, _dp(lo), _dp(hi), _dp(p), npar, period, mixed_mode, bc,
+                               _dp(phi0), _dp(psi0), t0, dt, steps, _dp(lam), _dp(tgt), eps,
+                               ctypes.byref(val), _dp(grad)), "grad_cs")
+    return val.value, grad.reshape(4, 4)

@@ -111,6 +111,17 @@ double orc_max_speed(int dim, const long *ncell, const double *lo, const double 
                      int kind, const double *params, long nparams, double period,
                      double t);
 
+/* Complex-step derivatives (gals_oracle_cs.c) of a functional of the final
+ * state of a 2D GALS_VEL_STREAM_SIN advance with respect to the folded
+ * stream-function table S[m][n] (m, n = 1..4; grad[4*(m-1) + (n-1)]). The
+ * functional is sum(lam . u_T) over the 3 planes of lam (3N values) if lam is
+ * not NULL, else prod(h) sum (H_eps(phi_T) - H_eps(phi_target))^2. *value
+ * receives the functional. Runs 16 complex advances. */
+int orc_grad_cs(const long *ncell, const double *lo, const double *hi, const double *params,
+                long nparams, double period, int mixed_mode, int bc, const double *phi0,
+                const double *psi0, double t0, double dt, long steps, const double *lam,
+                const double *phi_target, double eps, double *value, double *grad);
+
 /* Number of OpenMP threads the oracle runs with (1 without OpenMP). */
 int orc_num_threads(void);
 
