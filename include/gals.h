@@ -172,6 +172,54 @@ int gals_norms(gals_ctx *ctx, const void *phi, const void *grad, const void *phi
                void *workspace, size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Derivatives (2D grids with GALS_VEL_STREAM_SIN fields). The advance is a
+ * chain of steps u_{n+1} = M(u_n; S), u = (phi, psi_x, psi_y), S the folded
+ * stream-function table: S[m][n] = sum of the amplitudes of the modes with
+ * wavenumbers (m, n), m, n = 1..4, so dF/da_k = dF/dS[m_k][n_k]. Each step is
+ * linear in u (sec. 4 steps 1-3, eq. superconsistency); gals_adjoint_step
+ * applies its transpose and adds the step's contribution to dF/dS, which
+ * differentiates the three Shu-Osher stages of the trace
+ * (Ex. ex:superconsistent_ShuOsher) with S. Adjoint states are FP64 and use
+ * the state layout (3 planes of plane_stride elements, lam_phi, lam_x,
+ * lam_y); dF/dS is 16 FP64 values in device memory, index 4 (m-1) + (n-1).
+ * The state adjoint sums with FP64 atomics, so its last bits vary from run to
+ * run; dF/dS is reduced in a fixed order. Other fields or 3D grids: ENOTSUP.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of a checkpoint store for `steps` steps saved every `every` steps:
+ * ceil(steps / every) states, each (1 + dim) planes rounded up to 256 B. */
+int gals_checkpoint_bytes(const gals_ctx *ctx, int64_t steps, int64_t every, size_t *bytes);
+/* As gals_advance (same workspace), and store the state before steps
+ * 0, every, 2 every, ... in ckpt (device, 256-byte aligned, caller-owned).
+ * Step n starts at t0 + n dt, exactly as in gals_advance. Async. */
+int gals_advance_save(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int64_t steps,
+                      int64_t every, void *ckpt, size_t ckpt_bytes, void *workspace,
+                      size_t workspace_bytes, void *stream);
+/* Workspace bytes of gals_adjoint with checkpoints every `every` steps (and,
+ * with every = 1, of gals_adjoint_step): the advance's workspace, `every`
+ * recomputed states, one adjoint state and the dF/dS partials. */
+int gals_adjoint_workspace_bytes(const gals_ctx *ctx, int64_t every, size_t *bytes);
+/* Reverse sweep of the advance stored by gals_advance_save (same t0, dt,
+ * steps, every, velocity): lam holds dF/du at the final state on entry and
+ * dF/du at the initial state on return; dS receives dF/dS (overwritten).
+ * Recomputes each segment of `every` states from its checkpoint. Async. */
+int gals_adjoint(gals_ctx *ctx, const void *ckpt, size_t ckpt_bytes, double t0, double dt,
+                 int64_t steps, int64_t every, double *lam, double *dS, void *workspace,
+                 size_t workspace_bytes, void *stream);
+/* One reverse step: (phi, grad) is the state at the start of the step (time
+ * t), lam_in = dF/du after the step, lam_out = dF/du before it (overwritten;
+ * must not overlap lam_in); dS += the step's dF/dS. Workspace: every = 1. */
+int gals_adjoint_step(gals_ctx *ctx, const void *phi, const void *grad, double t, double dt,
+                      const double *lam_in, double *lam_out, double *dS, void *workspace,
+                      size_t workspace_bytes, void *stream);
+/* Shape loss prod(h) sum over nodes (H_eps(phi) - H_eps(phi_ref))^2 with the
+ * smoothed Heaviside of gals_norms (2D); *loss on the host. If lam is not
+ * NULL it receives dloss/du (3 FP64 planes; psi parts 0), the seed of
+ * gals_adjoint. Synchronises the stream. */
+int gals_shape_loss(gals_ctx *ctx, const void *phi, const void *phi_ref, double eps, double *loss,
+                    double *lam, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batches: many independent 2D grids, each with its own sine stream-function
  * field (GALS_VEL_STREAM_SIN; all share one period), advanced together by one
  * persistent launch per step. The state of all problems is one buffer:

@@ -34,7 +34,9 @@ EXPORTS = ("gals_create", "gals_destroy", "gals_layout", "gals_workspace_bytes",
            "gals_norms", "gals_last_error", "gals_batch_create", "gals_batch_destroy",
            "gals_batch_layout", "gals_batch_workspace_bytes", "gals_batch_set_velocity",
            "gals_batch_set_tiles", "gals_batch_get_tiles", "gals_batch_advance",
-           "gals_batch_autotune")
+           "gals_batch_autotune", "gals_checkpoint_bytes", "gals_advance_save",
+           "gals_adjoint_workspace_bytes", "gals_adjoint", "gals_adjoint_step",
+           "gals_shape_loss")
 
 _lib = None
 
@@ -75,6 +77,12 @@ def lib():
     L.gals_batch_get_tiles.argtypes = [vp, PI]
     L.gals_batch_advance.argtypes = [vp, vp, d, d, i64, i, vp, sz, vp]
     L.gals_batch_autotune.argtypes = [vp, vp, d, i64, vp, sz, vp, PD]
+    L.gals_checkpoint_bytes.argtypes = [vp, i64, i64, ctypes.POINTER(sz)]
+    L.gals_advance_save.argtypes = [vp, vp, vp, d, d, i64, i64, vp, sz, vp, sz, vp]
+    L.gals_adjoint_workspace_bytes.argtypes = [vp, i64, ctypes.POINTER(sz)]
+    L.gals_adjoint.argtypes = [vp, vp, sz, d, d, i64, i64, vp, vp, vp, sz, vp]
+    L.gals_adjoint_step.argtypes = [vp, vp, vp, d, d, vp, vp, vp, vp, sz, vp]
+    L.gals_shape_loss.argtypes = [vp, vp, vp, d, PD, vp, vp, sz, vp]
     L.gals_last_error.argtypes = []
     L.gals_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -251,6 +259,102 @@ class Grid:
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                _stream_handle(stream, self._dev())))
         return np.array(out[:])
+
+    # ------------------------------------------------------------ derivatives
+    def empty_adjoint(self):
+        """Zero FP64 adjoint state (3, plane): lam_phi, lam_x, lam_y."""
+        import torch
+        return torch.zeros((3, self.plane), dtype=torch.float64, device=self._dev())
+
+    def checkpoint_bytes(self, steps, every):
+        b = ctypes.c_size_t()
+        check(lib().gals_checkpoint_bytes(self._ctx, int(steps), int(every), ctypes.byref(b)))
+        return b.value
+
+    def _adjoint_workspace(self, every):
+        import torch
+        b = ctypes.c_size_t()
+        check(lib().gals_adjoint_workspace_bytes(self._ctx, int(every), ctypes.byref(b)))
+        cache = getattr(self, "_adj_ws", None)
+        if cache is None or cache.numel() < b.value:
+            self._adj_ws = torch.empty(b.value, dtype=torch.uint8, device=self._dev())
+        return self._adj_ws
+
+    def advance_save(self, state, t0, dt, steps, every, ckpt=None, stream=None):
+        """Advance in place and return the checkpoint store (uint8 device
+        tensor) holding the state before steps 0, every, 2 every, ..."""
+        import torch
+        self._check_state(state)
+        need = self.checkpoint_bytes(steps, every)
+        if ckpt is None:
+            ckpt = torch.empty(max(need, 256), dtype=torch.uint8, device=self._dev())
+        ws = self.workspace()
+        check(lib().gals_advance_save(self._ctx, ctypes.c_void_p(state[0].data_ptr()),
+                                      ctypes.c_void_p(state[1].data_ptr()), float(t0), float(dt),
+                                      int(steps), int(every), ctypes.c_void_p(ckpt.data_ptr()),
+                                      ckpt.numel(), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                      _stream_handle(stream, self._dev())))
+        return ckpt
+
+    def _check_adjoint(self, lam):
+        import torch
+        if (lam.dtype != torch.float64 or tuple(lam.shape) != (3, self.plane)
+                or not lam.is_contiguous() or lam.device != self._dev()):
+            raise ValueError("adjoint state must be a contiguous (3, plane) float64 tensor on "
+                             "the grid's device")
+
+    def adjoint(self, ckpt, t0, dt, steps, every, lam, dS=None, stream=None):
+        """Reverse sweep: lam (dF/du at the final state) becomes dF/du at the
+        initial state, in place; returns dF/dS as a 16-value FP64 device
+        tensor (index 4 (m-1) + (n-1))."""
+        import torch
+        self._check_adjoint(lam)
+        if dS is None:
+            dS = torch.zeros(16, dtype=torch.float64, device=self._dev())
+        ws = self._adjoint_workspace(every)
+        check(lib().gals_adjoint(self._ctx, ctypes.c_void_p(ckpt.data_ptr()), ckpt.numel(),
+                                 float(t0), float(dt), int(steps), int(every),
+                                 ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(dS.data_ptr()),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                 _stream_handle(stream, self._dev())))
+        return dS
+
+    def adjoint_step(self, state, t, dt, lam_in, lam_out=None, dS=None, stream=None):
+        """One reverse step from time t; returns (lam_out, dS) with dS += the
+        step's dF/dS."""
+        import torch
+        self._check_state(state)
+        self._check_adjoint(lam_in)
+        if lam_out is None:
+            lam_out = self.empty_adjoint()
+        self._check_adjoint(lam_out)
+        if dS is None:
+            dS = torch.zeros(16, dtype=torch.float64, device=self._dev())
+        ws = self._adjoint_workspace(1)
+        check(lib().gals_adjoint_step(self._ctx, ctypes.c_void_p(state[0].data_ptr()),
+                                      ctypes.c_void_p(state[1].data_ptr()), float(t), float(dt),
+                                      ctypes.c_void_p(lam_in.data_ptr()),
+                                      ctypes.c_void_p(lam_out.data_ptr()),
+                                      ctypes.c_void_p(dS.data_ptr()),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                      _stream_handle(stream, self._dev())))
+        return lam_out, dS
+
+    def shape_loss(self, state, ref, eps, with_grad=True, stream=None):
+        """(loss, lam): the smoothed-Heaviside shape loss against ref and, if
+        with_grad, its derivative as an FP64 adjoint state (else None)."""
+        self._check_state(state)
+        self._check_state(ref)
+        lam = self.empty_adjoint() if with_grad else None
+        out = ctypes.c_double()
+        ws = self.workspace()
+        check(lib().gals_shape_loss(self._ctx, ctypes.c_void_p(state[0].data_ptr()),
+                                    ctypes.c_void_p(ref[0].data_ptr()), float(eps),
+                                    ctypes.byref(out),
+                                    ctypes.c_void_p(lam.data_ptr()) if lam is not None else None,
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    _stream_handle(stream, self._dev())))
+        return out.value, lam
 
 
 class Batch:

@@ -85,6 +85,51 @@ struct DeviceGuard {
 
 double time_factor(double period, double t) { return period > 0.0 ? cos(M_PI * t / period) : 1.0; }
 
+// Stream-function tables into the workspace (sine stream functions only).
+hipError_t launch_tables(const gals_ctx *ctx, void *workspace, hipStream_t s)
+{
+    if (ctx->vel_kind != GALS_VEL_STREAM_SIN) return hipSuccess;
+    char *ws = (char *)workspace;
+    return launch_stream_tables(ctx, ws + coltab_offset(ctx), ws + rowtab_offset(ctx), s);
+}
+
+// Steps n_begin .. n_end-1 of an advance from time t0 (step n starts at
+// t0 + n dt), ping-ponging through the workspace's state copy; the result
+// ends in (phi, grad). The tables must be in the workspace already.
+hipError_t advance_core(const gals_ctx *ctx, void *phi, void *grad, double t0, double dt,
+                        int64_t n_begin, int64_t n_end, void *workspace, hipStream_t s)
+{
+    const size_t pb = size_t(ctx->g.plane) * elem_size(ctx);
+    char *ws = (char *)workspace;
+    void *bufs[2][2] = {{phi, grad}, {ws, ws + pb}};
+    void *coltab = nullptr, *rowtab = nullptr;
+    if (ctx->vel_kind == GALS_VEL_STREAM_SIN) {
+        coltab = ws + coltab_offset(ctx);
+        rowtab = ws + rowtab_offset(ctx);
+    }
+    hipError_t e = hipSuccess;
+    for (int64_t n = n_begin; n < n_end; n++) {
+        const double t = t0 + double(n) * dt;
+        const double c1 = time_factor(ctx->period, t + dt);
+        const double c2 = time_factor(ctx->period, t);
+        const double c3 = time_factor(ctx->period, t + 0.5 * dt);
+        void **src = bufs[(n - n_begin) & 1], **dst = bufs[(n - n_begin + 1) & 1];
+        e = launch_step(ctx, src[0], src[1], dst[0], dst[1], dt, c1, c2, c3, coltab, rowtab, s);
+        if (e != hipSuccess) return e;
+    }
+    if ((n_end - n_begin) & 1) {
+        // the result sits in the workspace: copy the valid part of each plane back
+        const size_t es = elem_size(ctx);
+        const size_t w = size_t(ctx->g.n[0]) * es, p = size_t(ctx->g.pitch) * es;
+        const size_t rows = size_t(ctx->g.n[1]) * size_t(ctx->g.n[2]);
+        for (int a = 0; a <= ctx->dim && e == hipSuccess; a++) {
+            char *dstp = a == 0 ? (char *)phi : (char *)grad + size_t(a - 1) * pb;
+            e = hipMemcpy2DAsync(dstp, p, ws + size_t(a) * pb, p, w, rows, hipMemcpyDeviceToDevice, s);
+        }
+    }
+    return e;
+}
+
 template <typename T>
 void fill_vel(Vel<T> &v, int kind, int dim, const double *p, int64_t np)
 {
@@ -311,35 +356,9 @@ int gals_advance(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "gals_advance: pending HIP error");
     hipStream_t s = (hipStream_t)stream;
-    char *ws = (char *)workspace;
-    void *bufs[2][2] = {{phi, grad}, {ws, ws + pb}};
-    void *coltab = nullptr, *rowtab = nullptr;
-    if (ctx->vel_kind == GALS_VEL_STREAM_SIN) {
-        coltab = ws + coltab_offset(ctx);
-        rowtab = ws + rowtab_offset(ctx);
-        e = launch_stream_tables(ctx, coltab, rowtab, s);
-        if (e != hipSuccess) return hip_fail(e, "gals_advance: table launch");
-    }
-    for (int64_t n = 0; n < steps; n++) {
-        const double t = t0 + double(n) * dt;
-        const double c1 = time_factor(ctx->period, t + dt);
-        const double c2 = time_factor(ctx->period, t);
-        const double c3 = time_factor(ctx->period, t + 0.5 * dt);
-        void **src = bufs[n & 1], **dst = bufs[(n + 1) & 1];
-        e = launch_step(ctx, src[0], src[1], dst[0], dst[1], dt, c1, c2, c3, coltab, rowtab, s);
-        if (e != hipSuccess) return hip_fail(e, "gals_advance: step launch");
-    }
-    if (steps & 1) {
-        // the result sits in the workspace: copy the valid part of each plane back
-        const size_t w = size_t(ctx->g.n[0]) * es, p = size_t(ctx->g.pitch) * es;
-        const size_t rows = size_t(ctx->g.n[1]) * size_t(ctx->g.n[2]);
-        for (int a = 0; a <= ctx->dim; a++) {
-            char *dstp = a == 0 ? (char *)phi : (char *)grad + size_t(a - 1) * pb;
-            e = hipMemcpy2DAsync(dstp, p, ws + size_t(a) * pb, p, w, rows, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) return hip_fail(e, "gals_advance: copy back");
-        }
-    }
-    return GALS_OK;
+    e = launch_tables(ctx, workspace, s);
+    if (e == hipSuccess) e = advance_core(ctx, phi, grad, t0, dt, 0, steps, workspace, s);
+    return e == hipSuccess ? GALS_OK : hip_fail(e, "gals_advance: launch");
 }
 
 int gals_eval_points(gals_ctx *ctx, const void *phi, const void *grad, const double *pts,
@@ -422,6 +441,262 @@ int gals_norms(gals_ctx *ctx, const void *phi, const void *grad, const void *phi
     out[2] *= cellvol;
     out[4] *= cellvol;
     out[5] *= cellvol;
+    return GALS_OK;
+}
+
+
+/* ---------------------------------------------------------------------------
+ * Adjoint of the advance (2D sine stream-function fields).
+ * Workspace: [forward workspace | `every` segment states | one adjoint state
+ * (3 FP64 planes) | per-block partials of dF/dS (16 FP64 each)].
+ * ------------------------------------------------------------------------- */
+}  // extern "C"
+
+namespace {
+
+size_t seg_state_bytes(const gals_ctx *c) { return align256(state_bytes(c)); }
+size_t lam_bytes(const gals_ctx *c) { return 3 * size_t(c->g.plane) * sizeof(double); }
+
+size_t adj_seg_offset(const gals_ctx *c) { return align256(workspace_bytes(c)); }
+size_t adj_lam_offset(const gals_ctx *c, int64_t every)
+{
+    return adj_seg_offset(c) + size_t(every) * seg_state_bytes(c);
+}
+size_t adj_part_offset(const gals_ctx *c, int64_t every)
+{
+    return adj_lam_offset(c, every) + align256(lam_bytes(c));
+}
+size_t adj_workspace_bytes(const gals_ctx *c, int64_t every)
+{
+    return adj_part_offset(c, every) +
+           align256(sizeof(double) * 16 * size_t(adjoint_blocks(c)));
+}
+
+int64_t nsegments(int64_t steps, int64_t every) { return (steps + every - 1) / every; }
+
+int check_adjoint_ctx(const gals_ctx *ctx, const char *what)
+{
+    if (!ctx) return fail(GALS_EINVAL, "%s: NULL context", what);
+    if (!ctx->vel_set) return fail(GALS_EINVAL, "%s: no velocity set", what);
+    if (ctx->dim != 2 || ctx->vel_kind != GALS_VEL_STREAM_SIN)
+        return fail(GALS_ENOTSUP, "%s: the adjoint covers 2D GALS_VEL_STREAM_SIN fields", what);
+    return GALS_OK;
+}
+
+// Copy a state (phi plane, then dim gradient planes) to/from one contiguous
+// checkpoint slot.
+hipError_t copy_state(const gals_ctx *ctx, void *dphi, void *dgrad, const void *sphi,
+                      const void *sgrad, hipStream_t s)
+{
+    const size_t pb = size_t(ctx->g.plane) * elem_size(ctx);
+    hipError_t e = hipMemcpyAsync(dphi, sphi, pb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dgrad, sgrad, pb * size_t(ctx->dim), hipMemcpyDeviceToDevice, s);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gals_checkpoint_bytes(const gals_ctx *ctx, int64_t steps, int64_t every, size_t *bytes)
+{
+    if (!ctx || !bytes) return fail(GALS_EINVAL, "gals_checkpoint_bytes: NULL argument");
+    if (steps < 0 || every < 1) return fail(GALS_EINVAL, "gals_checkpoint_bytes: steps >= 0, every >= 1");
+    *bytes = size_t(nsegments(steps, every)) * seg_state_bytes(ctx);
+    return GALS_OK;
+}
+
+int gals_adjoint_workspace_bytes(const gals_ctx *ctx, int64_t every, size_t *bytes)
+{
+    if (!ctx || !bytes) return fail(GALS_EINVAL, "gals_adjoint_workspace_bytes: NULL argument");
+    if (every < 1 || every > (int64_t(1) << 20))
+        return fail(GALS_EINVAL, "gals_adjoint_workspace_bytes: every must be in [1, 2^20]");
+    *bytes = adj_workspace_bytes(ctx, every);
+    return GALS_OK;
+}
+
+int gals_advance_save(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int64_t steps,
+                      int64_t every, void *ckpt, size_t ckpt_bytes, void *workspace,
+                      size_t workspace_bytes_, void *stream)
+{
+    if (!ctx) return fail(GALS_EINVAL, "gals_advance_save: NULL context");
+    if (every < 1) return fail(GALS_EINVAL, "gals_advance_save: every must be >= 1");
+    if (!ckpt && steps > 0) return fail(GALS_EINVAL, "gals_advance_save: NULL checkpoint store");
+    size_t need = 0;
+    if (steps >= 0) need = size_t(nsegments(steps, every)) * seg_state_bytes(ctx);
+    if (steps > 0 && (ckpt_bytes < need || !aligned(ckpt, 256)))
+        return fail(GALS_EINVAL, "gals_advance_save: checkpoint store of %zu bytes, %zu needed "
+                                 "(256-byte aligned)", ckpt_bytes, need);
+    // the argument checks of gals_advance, without running it
+    int rc = gals_advance(ctx, phi, grad, t0, dt, 0, workspace, workspace_bytes_, stream);
+    if (rc != GALS_OK) return rc;
+    if (steps < 0) return fail(GALS_EINVAL, "gals_advance_save: steps < 0");
+    if (steps == 0) return GALS_OK;
+    const size_t pb = size_t(ctx->g.plane) * elem_size(ctx);
+    if (overlap(ckpt, ckpt_bytes, phi, pb) || overlap(ckpt, ckpt_bytes, grad, pb * ctx->dim) ||
+        overlap(ckpt, ckpt_bytes, workspace, workspace_bytes_))
+        return fail(GALS_EINVAL, "gals_advance_save: the checkpoint store overlaps another buffer");
+    if (ctx->device < 0) return fail(GALS_EINVAL, "gals_advance_save: host-only context (device -1)");
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "gals_advance_save: hipSetDevice");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gals_advance_save: pending HIP error");
+    hipStream_t s = (hipStream_t)stream;
+    e = launch_tables(ctx, workspace, s);
+    for (int64_t k = 0; k < nsegments(steps, every) && e == hipSuccess; k++) {
+        char *slot = (char *)ckpt + size_t(k) * seg_state_bytes(ctx);
+        e = copy_state(ctx, slot, slot + pb, phi, grad, s);
+        const int64_t n0 = k * every, n1 = n0 + every < steps ? n0 + every : steps;
+        if (e == hipSuccess) e = advance_core(ctx, phi, grad, t0, dt, n0, n1, workspace, s);
+    }
+    return e == hipSuccess ? GALS_OK : hip_fail(e, "gals_advance_save: launch");
+}
+
+int gals_adjoint(gals_ctx *ctx, const void *ckpt, size_t ckpt_bytes, double t0, double dt,
+                 int64_t steps, int64_t every, double *lam, double *dS, void *workspace,
+                 size_t workspace_bytes_, void *stream)
+{
+    int rc = check_adjoint_ctx(ctx, "gals_adjoint");
+    if (rc != GALS_OK) return rc;
+    if (!lam || !dS || !workspace) return fail(GALS_EINVAL, "gals_adjoint: NULL pointer");
+    if (!isfinite(dt) || !(dt > 0.0) || !isfinite(t0))
+        return fail(GALS_EINVAL, "gals_adjoint: dt must be finite and > 0, t0 finite");
+    if (steps < 0 || every < 1 || every > (int64_t(1) << 20))
+        return fail(GALS_EINVAL, "gals_adjoint: steps >= 0 and every in [1, 2^20]");
+    const size_t need_ck = size_t(nsegments(steps, every)) * seg_state_bytes(ctx);
+    if (steps > 0 && (!ckpt || ckpt_bytes < need_ck || !aligned(ckpt, 256)))
+        return fail(GALS_EINVAL, "gals_adjoint: checkpoint store of %zu bytes, %zu needed",
+                    ckpt_bytes, need_ck);
+    const size_t need = adj_workspace_bytes(ctx, every);
+    if (workspace_bytes_ < need || !aligned(workspace, 256))
+        return fail(GALS_EINVAL, "gals_adjoint: workspace of %zu bytes, %zu needed (256-byte aligned)",
+                    workspace_bytes_, need);
+    if (!aligned(lam, 8) || !aligned(dS, 8)) return fail(GALS_EINVAL, "gals_adjoint: misaligned pointer");
+    if (overlap(lam, lam_bytes(ctx), workspace, workspace_bytes_) ||
+        overlap(dS, 16 * sizeof(double), workspace, workspace_bytes_) ||
+        overlap(lam, lam_bytes(ctx), dS, 16 * sizeof(double)) ||
+        (steps > 0 && (overlap(ckpt, ckpt_bytes, workspace, workspace_bytes_) ||
+                       overlap(ckpt, ckpt_bytes, lam, lam_bytes(ctx)))))
+        return fail(GALS_EINVAL, "gals_adjoint: buffers overlap");
+    if (ctx->device < 0) return fail(GALS_EINVAL, "gals_adjoint: host-only context (device -1)");
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "gals_adjoint: hipSetDevice");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gals_adjoint: pending HIP error");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    const size_t pb = size_t(ctx->g.plane) * elem_size(ctx);
+    const size_t sb = seg_state_bytes(ctx);
+    char *seg = ws + adj_seg_offset(ctx);
+    double *lamA = lam, *lamB = (double *)(ws + adj_lam_offset(ctx, every));
+    double *part = (double *)(ws + adj_part_offset(ctx, every));
+    const int nblocks = int(adjoint_blocks(ctx));
+    void *coltab = ws + coltab_offset(ctx), *rowtab = ws + rowtab_offset(ctx);
+    e = launch_tables(ctx, workspace, s);
+    if (e == hipSuccess) e = launch_zero(part, int64_t(nblocks) * 16, s);
+    if (e == hipSuccess) e = launch_zero(dS, 16, s);
+    for (int64_t k = nsegments(steps, every) - 1; k >= 0 && e == hipSuccess; k--) {
+        const int64_t n0 = k * every, len = n0 + every < steps ? every : steps - n0;
+        // recompute the states of this segment from its checkpoint
+        const char *slot = (const char *)ckpt + size_t(k) * sb;
+        e = copy_state(ctx, seg, seg + pb, slot, slot + pb, s);
+        const void *coltab_c = coltab, *rowtab_c = rowtab;
+        for (int64_t q = 1; q < len && e == hipSuccess; q++) {
+            const double t = t0 + double(n0 + q - 1) * dt;
+            char *src = seg + size_t(q - 1) * sb, *dst = seg + size_t(q) * sb;
+            e = launch_step(ctx, src, src + pb, dst, dst + pb, dt,
+                            time_factor(ctx->period, t + dt), time_factor(ctx->period, t),
+                            time_factor(ctx->period, t + 0.5 * dt), coltab_c, rowtab_c, s);
+        }
+        // reverse sweep over the segment
+        for (int64_t q = len - 1; q >= 0 && e == hipSuccess; q--) {
+            const double t = t0 + double(n0 + q) * dt;
+            const char *u = seg + size_t(q) * sb;
+            e = launch_adjoint_step(ctx, u, u + pb, lamA, lamB, part, dt,
+                                    time_factor(ctx->period, t + dt), time_factor(ctx->period, t),
+                                    time_factor(ctx->period, t + 0.5 * dt), coltab, rowtab, s);
+            double *tmp = lamA;
+            lamA = lamB;
+            lamB = tmp;
+        }
+    }
+    if (e == hipSuccess && lamA != lam)
+        e = hipMemcpyAsync(lam, lamA, lam_bytes(ctx), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_fold_grad(part, nblocks, dS, s);
+    return e == hipSuccess ? GALS_OK : hip_fail(e, "gals_adjoint: launch");
+}
+
+int gals_adjoint_step(gals_ctx *ctx, const void *phi, const void *grad, double t, double dt,
+                      const double *lam_in, double *lam_out, double *dS, void *workspace,
+                      size_t workspace_bytes_, void *stream)
+{
+    int rc = check_adjoint_ctx(ctx, "gals_adjoint_step");
+    if (rc != GALS_OK) return rc;
+    if (!phi || !grad || !lam_in || !lam_out || !dS || !workspace)
+        return fail(GALS_EINVAL, "gals_adjoint_step: NULL pointer");
+    if (!isfinite(dt) || !(dt > 0.0) || !isfinite(t))
+        return fail(GALS_EINVAL, "gals_adjoint_step: dt must be finite and > 0, t finite");
+    const size_t need = adj_workspace_bytes(ctx, 1);
+    if (workspace_bytes_ < need || !aligned(workspace, 256))
+        return fail(GALS_EINVAL, "gals_adjoint_step: workspace of %zu bytes, %zu needed",
+                    workspace_bytes_, need);
+    const size_t es = elem_size(ctx), pb = size_t(ctx->g.plane) * es;
+    if (!aligned(phi, es) || !aligned(grad, es) || !aligned(lam_in, 8) || !aligned(lam_out, 8) ||
+        !aligned(dS, 8))
+        return fail(GALS_EINVAL, "gals_adjoint_step: misaligned pointer");
+    if (overlap(lam_in, lam_bytes(ctx), lam_out, lam_bytes(ctx)) ||
+        overlap(lam_out, lam_bytes(ctx), workspace, workspace_bytes_) ||
+        overlap(lam_out, lam_bytes(ctx), phi, pb) || overlap(lam_out, lam_bytes(ctx), grad, 2 * pb) ||
+        overlap(dS, 16 * sizeof(double), lam_out, lam_bytes(ctx)) ||
+        overlap(dS, 16 * sizeof(double), workspace, workspace_bytes_))
+        return fail(GALS_EINVAL, "gals_adjoint_step: buffers overlap");
+    if (ctx->device < 0) return fail(GALS_EINVAL, "gals_adjoint_step: host-only context (device -1)");
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "gals_adjoint_step: hipSetDevice");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gals_adjoint_step: pending HIP error");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    double *part = (double *)(ws + adj_part_offset(ctx, 1));
+    const int nblocks = int(adjoint_blocks(ctx));
+    e = launch_tables(ctx, workspace, s);
+    if (e == hipSuccess) e = launch_zero(part, int64_t(nblocks) * 16, s);
+    if (e == hipSuccess)
+        e = launch_adjoint_step(ctx, phi, grad, lam_in, lam_out, part, dt,
+                                time_factor(ctx->period, t + dt), time_factor(ctx->period, t),
+                                time_factor(ctx->period, t + 0.5 * dt), ws + coltab_offset(ctx),
+                                ws + rowtab_offset(ctx), s);
+    if (e == hipSuccess) e = launch_fold_grad(part, nblocks, dS, s);
+    return e == hipSuccess ? GALS_OK : hip_fail(e, "gals_adjoint_step: launch");
+}
+
+int gals_shape_loss(gals_ctx *ctx, const void *phi, const void *phi_ref, double eps, double *loss,
+                    double *lam, void *workspace, size_t workspace_bytes_, void *stream)
+{
+    if (!ctx || !phi || !phi_ref || !loss || !workspace)
+        return fail(GALS_EINVAL, "gals_shape_loss: NULL argument");
+    if (ctx->dim != 2) return fail(GALS_ENOTSUP, "gals_shape_loss: 2D grids only");
+    if (!isfinite(eps) || !(eps > 0.0)) return fail(GALS_EINVAL, "gals_shape_loss: eps must be > 0");
+    if (!aligned(workspace, 256) || workspace_bytes_ < workspace_bytes(ctx))
+        return fail(GALS_EINVAL, "gals_shape_loss: workspace too small or misaligned");
+    if (lam && (!aligned(lam, 8) || overlap(lam, lam_bytes(ctx), workspace, workspace_bytes_)))
+        return fail(GALS_EINVAL, "gals_shape_loss: lam misaligned or overlapping the workspace");
+    if (ctx->device < 0) return fail(GALS_EINVAL, "gals_shape_loss: host-only context (device -1)");
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "gals_shape_loss: hipSetDevice");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gals_shape_loss: pending HIP error");
+    double *part = (double *)((char *)workspace + partial_offset(ctx));
+    double *res = part + size_t(kRedBlocks) * kRedSlots;
+    hipStream_t s = (hipStream_t)stream;
+    e = launch_heaviside_loss(ctx, phi, phi_ref, eps, lam, part, res, s);
+    if (e != hipSuccess) return hip_fail(e, "gals_shape_loss: launch");
+    const int rc = finish_reduction(ctx, res, loss, 1, s, "gals_shape_loss: copy");
+    if (rc != GALS_OK) return rc;
+    double cellvol = 1.0;
+    for (int a = 0; a < ctx->dim; a++) cellvol *= ctx->g.h[a];
+    *loss *= cellvol;
     return GALS_OK;
 }
 

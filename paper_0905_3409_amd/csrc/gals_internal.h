@@ -110,6 +110,19 @@ hipError_t launch_step(const gals_ctx *ctx, const void *phi, const void *grad, v
 // Per-column / per-row stream-function tables (GALS_VEL_STREAM_SIN only).
 hipError_t launch_stream_tables(const gals_ctx *ctx, void *coltab, void *rowtab, hipStream_t s);
 
+// Adjoint of the stream-function step and the shape loss (adjoint.hip).
+// adjoint_blocks: blocks of the adjoint launch (16 partials each).
+unsigned adjoint_blocks(const gals_ctx *ctx);
+hipError_t launch_adjoint_step(const gals_ctx *ctx, const void *phi, const void *grad,
+                               const double *lam_in, double *lam_out, double *partials,
+                               double dt, double c1, double c2, double c3, const void *coltab,
+                               const void *rowtab, hipStream_t s);
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+hipError_t launch_fold_grad(const double *partials, int nparts, double *out, hipStream_t s);
+hipError_t launch_heaviside_loss(const gals_ctx *ctx, const void *phi, const void *phi_ref,
+                                 double eps, double *lam, double *partials, double *out,
+                                 hipStream_t s);
+
 // Batched stream-function problems (batch.hip). probs/tiles are device arrays.
 hipError_t launch_batch_tables(int prec, const void *probs_f64, int nprob, int max_entries,
                                void *tab, hipStream_t s);

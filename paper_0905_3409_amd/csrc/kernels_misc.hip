@@ -1,6 +1,7 @@
 // Point evaluation (value, normal, curvature) and deterministic FP64
 // reductions (error norms, shape error, volume, max speed) for gfx950.
 #include "hermite.h"
+#include "reduce.h"
 
 namespace gals {
 
@@ -92,51 +93,6 @@ hipError_t launch_eval(const gals_ctx *ctx, const void *phi, const void *grad, c
                                                         curv, s);
 }
 
-// ---------------------------------------------------------------------------
-// Deterministic reductions: a fixed grid of kRedBlocks blocks walks the nodes
-// with a fixed stride; each block reduces its slots (wave64 shuffles, then the
-// four waves in order) to one partial; a single block then folds the partials
-// in a fixed order. Bit b of maxmask selects max (set) or sum (clear) for
-// slot b.
-// ---------------------------------------------------------------------------
-template <int NS>
-__device__ __forceinline__ void block_reduce(double *acc, unsigned maxmask, double *out)
-{
-    __shared__ double sm[kBlock / 64][NS];
-#pragma unroll
-    for (int s = 0; s < NS; s++) {
-        double a = acc[s];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double o = __shfl_xor(a, off, 64);
-            a = ((maxmask >> s) & 1) ? fmax(a, o) : a + o;
-        }
-        acc[s] = a;
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int s = 0; s < NS; s++) sm[w][s] = acc[s];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int s = 0; s < NS; s++) {
-            double a = sm[0][s];
-            for (int k = 1; k < kBlock / 64; k++)
-                a = ((maxmask >> s) & 1) ? fmax(a, sm[k][s]) : a + sm[k][s];
-            out[s] = a;
-        }
-    }
-}
-
-__device__ __forceinline__ double heaviside_eps(double s, double eps)
-{
-    if (s < -eps) return 0.0;
-    if (s > eps) return 1.0;
-    return 0.5 * (1.0 + s / eps + sin(kPi * s / eps) / kPi);
-}
-
 __device__ __forceinline__ int64_t node_offset(const Geom &g, int64_t id)
 {
     const int64_t i = id % g.n[0];
@@ -176,23 +132,6 @@ __global__ __launch_bounds__(kBlock) void k_norms(Geom g, const T *__restrict__ 
         acc[7] = fmax(acc[7], fabs(r));
     }
     block_reduce<8>(acc, kNormsMax, partials + int64_t(blockIdx.x) * kRedSlots);
-}
-
-template <int NS>
-__global__ __launch_bounds__(kBlock) void k_fold(const double *__restrict__ partials, int nparts,
-                                                 unsigned maxmask, double *__restrict__ out)
-{
-    double acc[NS];
-#pragma unroll
-    for (int s = 0; s < NS; s++) acc[s] = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += kBlock) {
-#pragma unroll
-        for (int s = 0; s < NS; s++) {
-            const double v = partials[int64_t(b) * kRedSlots + s];
-            acc[s] = ((maxmask >> s) & 1) ? fmax(acc[s], v) : acc[s] + v;
-        }
-    }
-    block_reduce<NS>(acc, maxmask, out);
 }
 
 hipError_t launch_norms(const gals_ctx *ctx, const void *phi, const void *grad,

@@ -127,17 +127,25 @@ __device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J, 
     }
 }
 
-// One GA-CIR step at node (i, j) of a grid with a sine stream-function field:
-// the node's jet from the column row U and the table row Y, the three
-// Shu-Osher stages, the superconsistent Jacobian, the FP64 foot in cell
-// units, the boundary treatment, the gather and the bicubic update.
-template <typename T, int MIX, bool TAYLOR, class P>
-__device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Stage<T> &st,
-                                            double dt, const T *__restrict__ U,
-                                            const T *__restrict__ Y, Rsrc rphi, Rsrc rgx,
-                                            Rsrc rgy, T *__restrict__ phi_o,
-                                            T *__restrict__ gx_o, T *__restrict__ gy_o, int i,
-                                            int j)
+// The characteristic trace of node (i, j) for a sine stream-function field
+// (the forward step and its adjoint both start from it): the stage
+// velocities and velocity Jacobians, the offsets of the stage points from the
+// node, the superconsistent Jacobian J of the foot map, and the foot after
+// the boundary treatment, split into a cell and a local coordinate.
+template <typename T>
+struct StreamFoot {
+    T v0[2], v1[2], v2[2], A0[4], A1[4], A2[4], J[4];
+    T d1[2], d2[2];  // stage-2 and stage-3 points minus the node
+    unsigned out;    // bit a: the foot left the domain along axis a (Neumann)
+    int cell[2];
+    double xi[2];
+};
+
+template <typename T, bool TAYLOR, class P>
+__device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const Stage<T> &st,
+                                             double dt, const T *__restrict__ U,
+                                             const T *__restrict__ Y, int i, int j,
+                                             StreamFoot<T> &f)
 {
     StreamJet<T> jet;
     {
@@ -152,53 +160,63 @@ __device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Sta
     const double x0 = g.lo[0] + double(i) * g.h[0], y0 = g.lo[1] + double(j) * g.h[1];
     const T dtT = T(dt);
     // stage 1 at the node, time t + dt
-    T v0[2], A0[4];
-    from_stream(jet.d10, jet.d01, jet.d20, jet.d11, jet.d02, st.c1, v0, A0);
+    from_stream(jet.d10, jet.d01, jet.d20, jet.d11, jet.d02, st.c1, f.v0, f.A0);
     // stage 2 at x1 = x - dt v0, time t
-    T v1[2], A1[4];
-    stream_stage<T, TAYLOR>(p, jet, x0, y0, -dtT * v0[0], -dtT * v0[1], st.c2, v1, A1);
+    f.d1[0] = -dtT * f.v0[0];
+    f.d1[1] = -dtT * f.v0[1];
+    stream_stage<T, TAYLOR>(p, jet, x0, y0, f.d1[0], f.d1[1], st.c2, f.v1, f.A1);
     // stage 3 at x2 = x - dt (v0 + v1) / 4, time t + dt/2
-    T v2[2], A2[4];
-    stream_stage<T, TAYLOR>(p, jet, x0, y0, -dtT * (T(0.25) * v0[0] + T(0.25) * v1[0]),
-                            -dtT * (T(0.25) * v0[1] + T(0.25) * v1[1]), st.c3, v2, A2);
-    T J[4];
-    jacobian_chain<T, 2>(A0, A1, A2, dtT, J);
+    f.d2[0] = -dtT * (T(0.25) * f.v0[0] + T(0.25) * f.v1[0]);
+    f.d2[1] = -dtT * (T(0.25) * f.v0[1] + T(0.25) * f.v1[1]);
+    stream_stage<T, TAYLOR>(p, jet, x0, y0, f.d2[0], f.d2[1], st.c3, f.v2, f.A2);
+    jacobian_chain<T, 2>(f.A0, f.A1, f.A2, dtT, f.J);
 
     // foot in cell units, FP64: s = node - dt (v0/6 + v1/6 + 2 v2/3) / h
     double s[2];
-    s[0] = double(i) - dt * (double(v0[0]) * (1.0 / 6.0) + double(v1[0]) * (1.0 / 6.0) +
-                             double(v2[0]) * (2.0 / 3.0)) * g.inv_h[0];
-    s[1] = double(j) - dt * (double(v0[1]) * (1.0 / 6.0) + double(v1[1]) * (1.0 / 6.0) +
-                             double(v2[1]) * (2.0 / 3.0)) * g.inv_h[1];
-    unsigned out = 0;
-    int cell[2];
-    double xi[2];
+    s[0] = double(i) - dt * (double(f.v0[0]) * (1.0 / 6.0) + double(f.v1[0]) * (1.0 / 6.0) +
+                             double(f.v2[0]) * (2.0 / 3.0)) * g.inv_h[0];
+    s[1] = double(j) - dt * (double(f.v0[1]) * (1.0 / 6.0) + double(f.v1[1]) * (1.0 / 6.0) +
+                             double(f.v2[1]) * (2.0 / 3.0)) * g.inv_h[1];
+    f.out = 0;
 #pragma unroll
     for (int a = 0; a < 2; a++) {
         if (g.bc == GALS_BC_NEUMANN) {
-            if (s[a] < 0.0) { s[a] = 0.0; out |= 1u << a; }
-            else if (s[a] > double(g.nc[a])) { s[a] = double(g.nc[a]); out |= 1u << a; }
+            if (s[a] < 0.0) { s[a] = 0.0; f.out |= 1u << a; }
+            else if (s[a] > double(g.nc[a])) { s[a] = double(g.nc[a]); f.out |= 1u << a; }
         }
         // cell index clamped to [0, nc-1], local coordinate unclamped
         const double fl = fmin(fmax(floor(s[a]), 0.0), double(g.nc[a] - 1));
-        cell[a] = int(fl);
-        xi[a] = s[a] - fl;
+        f.cell[a] = int(fl);
+        f.xi[a] = s[a] - fl;
     }
+}
 
+// One GA-CIR step at node (i, j) of a grid with a sine stream-function field:
+// the trace, the gather and the bicubic update.
+template <typename T, int MIX, bool TAYLOR, class P>
+__device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Stage<T> &st,
+                                            double dt, const T *__restrict__ U,
+                                            const T *__restrict__ Y, Rsrc rphi, Rsrc rgx,
+                                            Rsrc rgy, T *__restrict__ phi_o,
+                                            T *__restrict__ gx_o, T *__restrict__ gy_o, int i,
+                                            int j)
+{
+    StreamFoot<T> f;
+    stream_trace<T, TAYLOR>(g, p, st, dt, U, Y, i, j, f);
     T d[4][4];
-    gather2d<T, MIX>(g, rphi, rgx, rgy, cell[0], cell[1], d);
+    gather2d<T, MIX>(g, rphi, rgx, rgy, f.cell[0], f.cell[1], d);
     Basis<T> bx, by;
-    basis<T, false>(T(xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
-    basis<T, false>(T(xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
+    basis<T, false>(T(f.xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
+    basis<T, false>(T(f.xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
     T H, Hx, Hy;
     hermite2d(d, bx, by, H, Hx, Hy);
-    if (out & 1u) Hx = T(0);
-    if (out & 2u) Hy = T(0);
+    if (f.out & 1u) Hx = T(0);
+    if (f.out & 2u) Hy = T(0);
 
     const int64_t o = int64_t(j) * g.pitch + i;
     phi_o[o] = H;
-    gx_o[o] = J[0] * Hx + J[2] * Hy;
-    gy_o[o] = J[1] * Hx + J[3] * Hy;
+    gx_o[o] = f.J[0] * Hx + f.J[2] * Hy;
+    gy_o[o] = f.J[1] * Hx + f.J[3] * Hy;
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin by id, and each XCD has its

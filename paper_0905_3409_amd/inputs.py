@@ -237,6 +237,28 @@ def batched_stream_circles(seed=4, nprob=512, steps=256, cfl=0.8, period=2.0,
                 dt=float(dt), steps=int(steps), t0=0.0, problems=probs, seed=seed, cfl=cfl)
 
 
+def adjoint_circles(seed=5, n=1024, steps=200, nmodes=16, cfl=0.8, target_seed=6):
+    """Parameter-gradient workload: 4 seeded circles (as stream_circles) on
+    n^2 cells, a steady sine stream function of nmodes modes with
+    (m, n) ~ U{1..4}^2 and amplitudes a ~ N(0, 0.05^2) (unscaled), target
+    amplitudes for the same modes drawn from target_seed, and
+    dt = cfl h / max |v_a| at the base amplitudes, steps steps."""
+    rng = np.random.default_rng(seed)
+    ncell = (n, n)
+    centres = rng.uniform(0.2, 0.8, (4, 2))
+    radii = rng.uniform(0.05, 0.15, 4)
+    modes = rng.integers(1, 5, (nmodes, 2))
+    amps = rng.normal(0.0, 0.05, nmodes)
+    target = np.random.default_rng(target_seed).normal(0.0, 0.05, nmodes)
+    params = np.stack([amps, modes[:, 0], modes[:, 1]], axis=1).astype(np.float64).ravel()
+    vmax = _stream_speed_max(params, ncell)
+    dt = cfl * (1.0 / n) / vmax
+    phi, psi = sdf_union(node_grid(ncell), centres, radii)
+    return dict(name="adjoint_circles", ncell=ncell, modes=modes, amps=amps, target_amps=target,
+                dt=float(dt), steps=int(steps), period=0.0, t0=0.0, eps=1.5 / n, phi0=phi,
+                psi0=psi, seed=seed, target_seed=target_seed, cfl=cfl)
+
+
 def random_points(seed, npts, dim, lo=0.0, hi=1.0):
     """npts uniform points, shape (npts, dim)."""
     rng = np.random.default_rng(seed)

@@ -278,3 +278,63 @@ def test_batch_binding_layout_roundtrip():
     assert bt.nprob == 3 and bt.num_nodes() == 81 + 34 * 6 + 71 * 71
     assert list(bt.offset) == [0, 3 * bt.plane[0], 3 * (bt.plane[0] + bt.plane[1])]
     assert bt.total_elems == 3 * int(bt.plane.sum())
+
+
+def test_adjoint_entry_points_validate_on_a_host_only_context():
+    L = pkg.lib()
+    P = ctypes.POINTER(ctypes.c_double)
+    rc, ctx = _ctx(dim=2, ncell=(10, 7, 1), prec=pkg.F64)
+    assert rc == pkg.OK
+    b = ctypes.c_size_t()
+    nodes = (ctypes.c_int64 * 2)()
+    pitch, plane = ctypes.c_int64(), ctypes.c_int64()
+    L.gals_layout(ctx, nodes, ctypes.byref(pitch), ctypes.byref(plane))
+    state_b = -(-3 * plane.value * 8 // 256) * 256
+    assert L.gals_checkpoint_bytes(ctx, 200, 20, ctypes.byref(b)) == pkg.OK
+    assert b.value == 10 * state_b
+    assert L.gals_checkpoint_bytes(ctx, 201, 20, ctypes.byref(b)) == pkg.OK
+    assert b.value == 11 * state_b
+    assert L.gals_checkpoint_bytes(ctx, 5, 0, ctypes.byref(b)) == pkg.EINVAL
+    assert L.gals_adjoint_workspace_bytes(ctx, 0, ctypes.byref(b)) == pkg.EINVAL
+    ws1, ws20 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.gals_adjoint_workspace_bytes(ctx, 1, ctypes.byref(ws1)) == pkg.OK
+    assert L.gals_adjoint_workspace_bytes(ctx, 20, ctypes.byref(ws20)) == pkg.OK
+    assert ws20.value - ws1.value == 19 * state_b
+    lam, dS, ws = ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 31), ctypes.c_void_p(1 << 32)
+    ck = ctypes.c_void_p(1 << 33)
+    args = (ck, 10 * state_b, 0.0, 0.01, 200, 20, lam, dS, ws, ws20.value, None)
+    # no velocity yet
+    assert L.gals_adjoint(ctx, *args) == pkg.EINVAL
+    good = np.array([0.01, 1, 2], dtype=np.float64)
+    assert L.gals_set_velocity(ctx, pkg.AFFINE, np.zeros(8).ctypes.data_as(P), 8, 0.0) == pkg.OK
+    assert L.gals_adjoint(ctx, *args) == pkg.ENOTSUP  # only sine stream functions
+    assert L.gals_set_velocity(ctx, pkg.STREAM_SIN, good.ctypes.data_as(P), 3, 0.0) == pkg.OK
+    bad = list(args)
+    bad[1] = 10 * state_b - 1  # checkpoint store too small
+    assert L.gals_adjoint(ctx, *bad) == pkg.EINVAL
+    bad = list(args)
+    bad[9] = ws20.value - 1  # workspace too small
+    assert L.gals_adjoint(ctx, *bad) == pkg.EINVAL
+    bad = list(args)
+    bad[6] = ctypes.c_void_p((1 << 32) + 512)  # lam inside the workspace
+    assert L.gals_adjoint(ctx, *bad) == pkg.EINVAL
+    bad = list(args)
+    bad[3] = 0.0  # dt
+    assert L.gals_adjoint(ctx, *bad) == pkg.EINVAL
+    assert L.gals_adjoint(ctx, *args) == pkg.EINVAL  # host-only context
+    assert b"host-only" in L.gals_last_error()
+    st = ctypes.c_void_p(1 << 34)
+    lam2 = ctypes.c_void_p((1 << 30) + 8)  # overlaps lam
+    assert L.gals_adjoint_step(ctx, st, st, 0.0, 0.01, lam, lam2, dS, ws, ws1.value,
+                               None) == pkg.EINVAL
+    out = ctypes.c_double()
+    assert L.gals_shape_loss(ctx, st, st, 0.0, ctypes.byref(out), None, ws, 1 << 30,
+                             None) == pkg.EINVAL  # eps
+    L.gals_destroy(ctx)
+    rc, ctx3 = _ctx(dim=3, ncell=(4, 4, 4), prec=pkg.F64)
+    assert L.gals_shape_loss(ctx3, st, st, 0.1, ctypes.byref(out), None, ws, 1 << 30,
+                             None) == pkg.ENOTSUP
+    assert L.gals_set_velocity(ctx3, pkg.LEVEQUE3D, None, 0, 0.0) == pkg.OK
+    assert L.gals_adjoint_step(ctx3, st, st, 0.0, 0.01, lam, ctypes.c_void_p(1 << 35), dS, ws,
+                               1 << 30, None) == pkg.ENOTSUP
+    L.gals_destroy(ctx3)
