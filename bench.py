@@ -16,6 +16,11 @@ Prints one JSON line. Options: --gpus (only 1 is supported), --steps K,
 --warmup W, --no-cpu (skip the oracle baseline), --inner (time steps per
 benchmark step, default the workload's 1024).
 
+--workload adjoint times one gradient of the shape loss with respect to 16
+stream-function amplitudes on 1024^2 cells: a 200-step FP32 advance that
+keeps a checkpoint every 20 steps, the loss and its seed, and the reverse
+sweep (each segment recomputed from its checkpoint, then 20 adjoint steps).
+
 --workload batched times the many-problem case instead: 512 independent
 grids of round(2^U(5,9)) cells per side, each with its own circles and
 stream function, 256 steps of dt = 2/256 per benchmark step, advanced
@@ -54,6 +59,17 @@ def log(msg):
 STEP_HEADERS = ["gals_internal.h", "velocity.h", "hermite.h", "stream2d.h"]
 SINGLE_KERNEL_SOURCES = ["kernels_step.hip"] + STEP_HEADERS
 BATCH_KERNEL_SOURCES = ["batch.hip"] + STEP_HEADERS
+ADJ_KERNEL_SOURCES = ["adjoint.hip", "reduce.h"] + STEP_HEADERS
+# Floating-point operations per node of the FP32 adjoint step (FMA = 2):
+# trace 381, cross derivatives 8, Hermite weights with second derivatives 60,
+# bicubic value, gradient and Hessian 132, the state adjoint's cell shares
+# 152, seeds 28, reverse Jacobian chain 128, sin/cos at the 3 stage points
+# 192, mode terms 546, third derivatives 384, stage-position adjoints 72,
+# accumulation and block reduction 112 (FP64).
+ADJ_FLOPS_PER_NODE = 2195
+# read the state (3 x 4 B) and lam_next (3 x 8 B); zero-fill and
+# accumulate lam_prev (3 x 8 B written, and the atomics' read-modify-write)
+ADJ_BYTES_PER_NODE = 12 + 24 + 24 + 24
 
 
 def kernel_source_hash(files):
@@ -90,7 +106,7 @@ def main():
     ap.add_argument("--inner", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched"], default="single")
+    ap.add_argument("--workload", choices=["single", "batched", "adjoint"], default="single")
     ap.add_argument("--tiles", default="",
                     help="batched only: wave widths per size class, e.g. 64,0,16,64, "
                          "instead of the autotuner's choice")
@@ -112,6 +128,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
     dev = torch.device("cuda", 0)
     w = inputs.stream_circles()
     inner = args.inner or w["steps"]
@@ -345,6 +363,116 @@ def bench_batched(args):
         "hbm_gbps_algorithmic": gbps,
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_adjoint(args):
+    import numpy as np
+    import torch
+
+    import paper_0905_3409_amd as pkg
+    from paper_0905_3409_amd import inputs
+    from paper_0905_3409_amd.autograd import stream_params
+
+    w = inputs.adjoint_circles()
+    n = w["ncell"][0]
+    nodes = (n + 1) ** 2
+    steps, every, dt, eps = w["steps"], 20, w["dt"], w["eps"]
+    g = pkg.Grid(w["ncell"], dtype="float32")
+    g.set_velocity(pkg.STREAM_SIN, stream_params(w["target_amps"], w["modes"]), 0.0)
+    tgt = g.from_numpy(w["phi0"], w["psi0"])
+    g.advance(tgt, 0.0, dt, steps)
+    g.set_velocity(pkg.STREAM_SIN, stream_params(w["amps"], w["modes"]), 0.0)
+    st0 = g.from_numpy(w["phi0"], w["psi0"])
+    st = st0.clone()
+    ckpt = torch.empty(g.checkpoint_bytes(steps, every), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    log(f"workload {w['name']}: {n}^2 cells, {len(w['amps'])} amplitudes, {steps} steps, "
+        f"checkpoints every {every}")
+    if args.profile:
+        k = args.inner or 8
+        g.advance_save(st, 0.0, dt, k, k, ckpt)
+        _, lam = g.shape_loss(st, tgt, eps)
+        g.adjoint(ckpt, 0.0, dt, k, k, lam)
+        torch.cuda.synchronize()
+        log(f"profile: {k} forward steps, {k - 1} recomputed, {k} adjoint steps")
+        return 0
+
+    def gradient(ev=None):
+        st.copy_(st0)
+        if ev is not None:
+            ev[0].record(s)
+        g.advance_save(st, 0.0, dt, steps, every, ckpt)
+        if ev is not None:
+            ev[1].record(s)
+        loss, lam = g.shape_loss(st, tgt, eps)  # synchronises
+        if ev is not None:
+            ev[2].record(s)
+        dS = g.adjoint(ckpt, 0.0, dt, steps, every, lam)
+        if ev is not None:
+            ev[3].record(s)
+        torch.cuda.synchronize()
+        return loss, dS
+
+    for _ in range(args.warmup):
+        gradient()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        loss, dS = gradient(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    rev_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    # the reverse sweep recomputes steps - ceil(steps / every) forward steps;
+    # the rest of it is the adjoint launches (and their zero fills)
+    recompute = steps - (steps + every - 1) // every
+    step_us = fwd_ms * 1e3 / steps
+    adj_us = (rev_ms * 1e3 - recompute * step_us) / steps
+    log(f"gradient: {ms:.2f} ms (forward {fwd_ms:.2f} ms, reverse sweep {rev_ms:.2f} ms); "
+        f"forward step {step_us:.1f} us, adjoint step {adj_us:.1f} us; loss {loss:.6e}")
+    flops = nodes * ADJ_FLOPS_PER_NODE / (adj_us * 1e-6) / 1e12
+    roofline = {"bound": "alu", "achieved": flops, "peak": VALU_F32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": flops / VALU_F32_PEAK_TFLOPS,
+                "traffic": traffic_record("k_adjoint2d_stream_f32_1024.md", ADJ_KERNEL_SOURCES),
+                "kernel": "k_adjoint2d_stream<float, CENTRAL, taylor>",
+                "flops_per_launch": nodes * ADJ_FLOPS_PER_NODE, "avg_launch_us": adj_us,
+                "avg_launch_us_from": "reverse-sweep events minus the recomputed forward steps",
+                "bytes_per_launch": nodes * ADJ_BYTES_PER_NODE,
+                "hbm_gbps": nodes * ADJ_BYTES_PER_NODE / (adj_us * 1e-6) / 1e9}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        k_cpu = 2
+        a = time.perf_counter()
+        oracle.grad_cs(w["ncell"], (0.0, 0.0), (1.0, 1.0), stream_params(w["amps"], w["modes"]),
+                       0.0, w["phi0"], w["psi0"], 0.0, dt, k_cpu,
+                       phi_target=w["phi0"], eps=eps)
+        b = time.perf_counter()
+        per_grad = (b - a) * steps / k_cpu
+        cpu = {"value": 1.0 / per_grad, "unit": "gradients/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"complex-step gradient (16 complex advances) over the first {k_cpu} of "
+                         f"the {steps} steps at 1024^2, {b - a:.1f} s, scaled to {steps} steps"}
+        log(f"cpu oracle: {per_grad:.0f} s per gradient on {cpu['cores']} threads")
+    line = {
+        "metric": "GALS gradient evaluations/s (dL/da, 16 stream-function amplitudes)",
+        "value": 1e3 / ms, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "adjoint_circles: 1024^2 cells, 4 seeded circles, steady 16-mode "
+                               "sine stream function, 200 steps at CFL 0.8, checkpoints every "
+                               "20, smoothed-Heaviside loss against a seeded target",
+                   "grid_nodes": [n + 1, n + 1], "time_steps": steps, "checkpoint_every": every,
+                   "state": "f32", "adjoint_state": "f64", "seed": w["seed"]},
+        "forward_ms": fwd_ms, "reverse_ms": rev_ms, "forward_step_us": step_us,
+        "adjoint_step_us": adj_us,
+        "node_steps_per_s": nodes * (2 * steps + recompute) / (ms * 1e-3),
+        "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     return 0

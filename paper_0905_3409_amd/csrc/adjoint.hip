@@ -13,41 +13,26 @@
 //   * the state adjoint scatters lambda_phi W_q + mu . grad W_q onto the 16
 //     cell data q (the transpose of the interpolation), and the phi_xy data
 //     onto psi_y through the transpose of the central difference D_x;
-//   * the parameter derivative adds, per table entry p,
-//     (lambda_phi grad H + Hess H mu) . (m X'_p) + sum_ij J'_p[i][j] m_i H_i lambda_j,
-//     with X'_p, J'_p the derivatives of the foot and of J along S[m][n]
-//     (forward mode through the three Shu-Osher stages of
-//     Ex. ex:superconsistent_ShuOsher; the stage Jacobians differentiate into
-//     the third derivatives of s).
+//   * the parameter derivative seeds the foot with Xbar = m (lambda_phi grad H
+//     + Hess H mu) and the Jacobian with Jbar[i][j] = m_i H_i lambda_j, runs
+//     both back through the three Shu-Osher stages of
+//     Ex. ex:superconsistent_ShuOsher (reverse mode: the stage positions
+//     pick up grad v and the third derivatives of s), and reads off
+//     dF/dS[m][n] = sum over stages c_k (vbar_k . v_mn(x_k) + Abar_k : grad v_mn(x_k)).
 // The state adjoint is accumulated with FP64 atomics (its summation order is
 // not fixed); the parameter derivative with a fixed-order block reduction.
+// With CLEAR the kernel zeroes lam_in as it reads it, so lam_in can receive
+// the next (earlier) step's scatter without a separate fill.
 #include "reduce.h"
 #include "stream2d.h"
 
 namespace gals {
 
-// v and grad v (J form, G[i][j] = dv_i/dx_j) of the single mode
-// sin(M x) sin(N y), M = (m+1) pi, N = (n+1) pi, from sin/cos of k pi x, y.
-template <typename T>
-__device__ __forceinline__ void mode_field(int m, int n, const T *sx, const T *cx, const T *sy,
-                                           const T *cy, T *v, T *G)
-{
-    const T M = T((m + 1) * kPi), N = T((n + 1) * kPi);
-    const T s_x = M * cx[m] * sy[n], s_y = N * sx[m] * cy[n];
-    const T s_xx = -M * M * sx[m] * sy[n], s_xy = M * N * cx[m] * cy[n];
-    const T s_yy = -N * N * sx[m] * sy[n];
-    v[0] = -s_y;
-    v[1] = s_x;
-    G[0] = -s_xy;
-    G[1] = -s_yy;
-    G[2] = s_xx;
-    G[3] = s_xy;
-}
-
-// Third derivatives (s_xxx, s_xxy, s_xyy, s_yyy) of the whole field.
-template <typename T>
-__device__ __forceinline__ void third_derivs(const T (&S)[4][4], const T *sx, const T *cx,
-                                             const T *sy, const T *cy, T *t)
+// Third derivatives (s_xxx, s_xxy, s_xyy, s_yyy) of the whole field, from
+// the tables S, SQ = S n pi, SR = S (n pi)^2.
+template <typename T, class P>
+__device__ __forceinline__ void third_derivs(const P &p, const T *sx, const T *cx, const T *sy,
+                                             const T *cy, T *t)
 {
     t[0] = t[1] = t[2] = t[3] = T(0);
 #pragma unroll
@@ -56,27 +41,66 @@ __device__ __forceinline__ void third_derivs(const T (&S)[4][4], const T *sx, co
         T Py = T(0), Qy = T(0), Ry = T(0), Ty = T(0);
 #pragma unroll
         for (int n = 0; n < 4; n++) {
-            const T N = T((n + 1) * kPi);
-            Py += S[m][n] * sy[n];
-            Qy += S[m][n] * N * cy[n];
-            Ry += S[m][n] * N * N * sy[n];
-            Ty += S[m][n] * N * N * N * cy[n];
+            Py += p.S[m][n] * sy[n];
+            Qy += p.SQ[m][n] * cy[n];
+            Ry += p.SR[m][n] * sy[n];
+            Ty += p.SR[m][n] * T((n + 1) * kPi) * cy[n];
         }
-        t[0] -= M * M * M * cx[m] * Py;
-        t[1] -= M * M * sx[m] * Qy;
+        t[0] -= (M * M * M) * cx[m] * Py;
+        t[1] -= (M * M) * sx[m] * Qy;
         t[2] -= M * cx[m] * Ry;
         t[3] -= sx[m] * Ty;
     }
 }
 
-// d(grad v)/dx . delta in J form, from the third derivatives t.
+// sum_ik Abar[i][k] dG[i][k]/dx and /dy from the third derivatives t.
 template <typename T>
-__device__ __forceinline__ void grad_v_dir(const T *t, T dx, T dy, T *D)
+__device__ __forceinline__ void grad_v_adj(const T *t, const T *Ab, T &gx, T &gy)
 {
-    D[0] = -(t[1] * dx + t[2] * dy);
-    D[1] = -(t[2] * dx + t[3] * dy);
-    D[2] = t[0] * dx + t[1] * dy;
-    D[3] = t[1] * dx + t[2] * dy;
+    gx = -Ab[0] * t[1] - Ab[1] * t[2] + Ab[2] * t[0] + Ab[3] * t[1];
+    gy = -Ab[0] * t[2] - Ab[1] * t[3] + Ab[2] * t[1] + Ab[3] * t[2];
+}
+
+// dF/dS[m][n] += c (vbar . v_mn + Abar : G_mn) at one stage point, for all
+// 16 (m, n): with a = -vbar_x, b = vbar_y, e = Abar[3] - Abar[0],
+// the mode term is sin(Mx) (N a cos(Ny) + (N^2 Abar[1] - M^2 Abar[2]) sin(Ny))
+//                + cos(Mx) M (b sin(Ny) + N e cos(Ny)).
+template <typename T>
+__device__ __forceinline__ void mode_terms(T c, const T *vb, const T *Ab, const T *sx,
+                                           const T *cx, const T *sy, const T *cy, T (&acc)[16])
+{
+    const T a = -c * vb[0], b = c * vb[1], e = c * (Ab[3] - Ab[0]);
+    const T d1 = c * Ab[1], d2 = -c * Ab[2];
+#pragma unroll
+    for (int n = 0; n < 4; n++) {
+        const T N = T((n + 1) * kPi);
+        const T ya = N * a * cy[n], yd = N * N * d1 * sy[n], ye = d2 * sy[n];
+        const T yb = b * sy[n], yc = N * e * cy[n];
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            const T M = T((m + 1) * kPi);
+            acc[4 * m + n] += sx[m] * (ya + yd + (M * M) * ye) + cx[m] * (M * (yb + yc));
+        }
+    }
+}
+
+// C = A B^T and C = A^T B for 2 x 2 matrices stored row-major.
+template <typename T>
+__device__ __forceinline__ void mul2_abt(const T *A, const T *B, T *C)
+{
+    C[0] = A[0] * B[0] + A[1] * B[1];
+    C[1] = A[0] * B[2] + A[1] * B[3];
+    C[2] = A[2] * B[0] + A[3] * B[1];
+    C[3] = A[2] * B[2] + A[3] * B[3];
+}
+
+template <typename T>
+__device__ __forceinline__ void mul2_atb(const T *A, const T *B, T *C)
+{
+    C[0] = A[0] * B[0] + A[2] * B[2];
+    C[1] = A[0] * B[1] + A[2] * B[3];
+    C[2] = A[1] * B[0] + A[3] * B[2];
+    C[3] = A[1] * B[1] + A[3] * B[3];
 }
 
 template <typename T>
@@ -90,12 +114,46 @@ __device__ __forceinline__ void mul2(const T *A, const T *B, T *C)
 
 __device__ __forceinline__ void scatter(double *p, double v) { unsafeAtomicAdd(p, v); }
 
-template <typename T, int MIX, bool TAYLOR>
+// LDS tile of the block's scatter: fields x nodes, nodes per row x rows.
+constexpr int kTileW = 96, kTileH = 12;
+
+// The transpose of the gather: dbar[v][alpha] for corner v = vx + 2 vy of
+// cell (c0, c1) goes to phi, psi_x, psi_y of that corner and, for the cross
+// derivative phi_xy = D_x psi_y, to psi_y of the difference stencil (central
+// inside, one-sided 3-point at node 0 and node nc). add(field, x, y, value).
+template <int MIX, class Add>
+__device__ __forceinline__ void emit_scatter(const double (&dbar)[4][4], int c0, int c1, int nc,
+                                             double inv2h, Add add)
+{
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        const int x = c0 + (v & 1), y = c1 + (v >> 1);
+        add(0, x, y, dbar[v][0]);
+        add(1, x, y, dbar[v][1]);
+        add(2, x, y, dbar[v][2]);
+        if constexpr (MIX == GALS_MIXED_CENTRAL) {
+            const double c = dbar[v][3] * inv2h;
+            if (x == 0) {
+                add(2, 0, y, -3.0 * c);
+                add(2, 1, y, 4.0 * c);
+                add(2, 2, y, -c);
+            } else if (x == nc) {
+                add(2, x, y, 3.0 * c);
+                add(2, x - 1, y, -4.0 * c);
+                add(2, x - 2, y, c);
+            } else {
+                add(2, x + 1, y, c);
+                add(2, x - 1, y, -c);
+            }
+        }
+    }
+}
+
+template <typename T, int MIX, bool TAYLOR, bool CLEAR>
 __global__ __launch_bounds__(kBlock) void k_adjoint2d_stream(
     Geom g, Vel<T> p, Stage<T> st, double dt, const T *__restrict__ coltab,
     const T *__restrict__ rowtab, const T *__restrict__ phi, const T *__restrict__ grad,
-    const double *__restrict__ lam_in, double *__restrict__ lam_out,
-    double *__restrict__ partials)
+    double *__restrict__ lam_in, double *__restrict__ lam_out, double *__restrict__ partials)
 {
     const unsigned tiles_x = (unsigned(g.n[0]) + 63u) / 64u;
     const unsigned tiles = tiles_x * ((unsigned(g.n[1]) + 3u) / 4u);
@@ -106,13 +164,21 @@ __global__ __launch_bounds__(kBlock) void k_adjoint2d_stream(
     double gacc[16];
 #pragma unroll
     for (int q = 0; q < 16; q++) gacc[q] = 0.0;
+    double dbar[4][4];
+    int cell0 = 0, cell1 = 0;
+    const bool valid = in_grid && i < g.n[0] && j < g.n[1];
 
-    if (in_grid && i < g.n[0] && j < g.n[1]) {
+    if (valid) {
         StreamFoot<T> f;
         stream_trace<T, TAYLOR>(g, p, st, dt, coltab + int64_t(i) * kJet,
                                 rowtab + int64_t(j) * kJet, i, j, f);
         const int64_t o = int64_t(j) * g.pitch + i;
         const double lf = lam_in[o], lx = lam_in[o + g.plane], ly = lam_in[o + 2 * g.plane];
+        if constexpr (CLEAR) {
+            lam_in[o] = 0.0;
+            lam_in[o + g.plane] = 0.0;
+            lam_in[o + 2 * g.plane] = 0.0;
+        }
 
         T d[4][4];
         gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(grad, g.plane),
@@ -127,67 +193,28 @@ __global__ __launch_bounds__(kBlock) void k_adjoint2d_stream(
         const double mu0 = m0 * (double(f.J[0]) * lx + double(f.J[1]) * ly);
         const double mu1 = m1 * (double(f.J[2]) * lx + double(f.J[3]) * ly);
 
-        // ---- state adjoint: transpose of the gather and the interpolation
-        double *Lphi = lam_out, *Lx = lam_out + g.plane, *Ly = lam_out + 2 * g.plane;
-        const double inv2h = double(T(0.5 * g.inv_h[0]));
+        // ---- state adjoint: the cell data's share, dbar[v][alpha] =
+        // lambda_phi W + mu . grad W (scattered below)
+        cell0 = f.cell[0];
+        cell1 = f.cell[1];
 #pragma unroll
-        for (int vy = 0; vy < 2; vy++) {
-            const int64_t row = int64_t(f.cell[1] + vy) * g.pitch;
+        for (int v = 0; v < 4; v++)
 #pragma unroll
-            for (int vx = 0; vx < 2; vx++) {
-                const int ci = f.cell[0] + vx;
-                double db[4];
-#pragma unroll
-                for (int a = 0; a < 4; a++) {
-                    const int kx = vx + 2 * (a & 1), ky = vy + 2 * (a >> 1);
-                    db[a] = lf * double(bx.w[kx]) * double(by.w[ky]) +
-                            mu0 * double(bx.dw[kx]) * double(by.w[ky]) +
-                            mu1 * double(bx.w[kx]) * double(by.dw[ky]);
-                }
-                scatter(Lphi + row + ci, db[0]);
-                scatter(Lx + row + ci, db[1]);
-                scatter(Ly + row + ci, db[2]);
-                if constexpr (MIX == GALS_MIXED_CENTRAL) {
-                    // phi_xy at node ci = D_x psi_y: central inside, one-sided
-                    // 3-point at node 0 and node nc
-                    const double c = db[3] * inv2h;
-                    if (ci == 0) {
-                        scatter(Ly + row + 0, -3.0 * c);
-                        scatter(Ly + row + 1, 4.0 * c);
-                        scatter(Ly + row + 2, -c);
-                    } else if (ci == g.nc[0]) {
-                        scatter(Ly + row + ci, 3.0 * c);
-                        scatter(Ly + row + ci - 1, -4.0 * c);
-                        scatter(Ly + row + ci - 2, c);
-                    } else {
-                        scatter(Ly + row + ci + 1, c);
-                        scatter(Ly + row + ci - 1, -c);
-                    }
-                }
+            for (int a = 0; a < 4; a++) {
+                const int kx = (v & 1) + 2 * (a & 1), ky = (v >> 1) + 2 * (a >> 1);
+                dbar[v][a] = lf * double(bx.w[kx]) * double(by.w[ky]) +
+                             mu0 * double(bx.dw[kx]) * double(by.w[ky]) +
+                             mu1 * double(bx.w[kx]) * double(by.dw[ky]);
             }
-        }
 
-        // ---- parameter derivative
-        // r = lambda_phi grad H + Hess H mu,  P[i][j] = m_i H_i lambda_j
-        const double r0 = lf * double(Gr[0]) + double(Hs[0]) * mu0 + double(Hs[1]) * mu1;
-        const double r1 = lf * double(Gr[1]) + double(Hs[2]) * mu0 + double(Hs[3]) * mu1;
-        const double P[4] = {m0 * double(Gr[0]) * lx, m0 * double(Gr[0]) * ly,
-                             m1 * double(Gr[1]) * lx, m1 * double(Gr[1]) * ly};
-        const double x0 = g.lo[0] + double(i) * g.h[0], y0 = g.lo[1] + double(j) * g.h[1];
-        T sx0[4], cx0[4], sy0[4], cy0[4], sx1[4], cx1[4], sy1[4], cy1[4];
-        T sx2[4], cx2[4], sy2[4], cy2[4];
-        sincos_multiples(T(x0), sx0, cx0);
-        sincos_multiples(T(y0), sy0, cy0);
-        sincos_multiples(T(x0 + double(f.d1[0])), sx1, cx1);
-        sincos_multiples(T(y0 + double(f.d1[1])), sy1, cy1);
-        sincos_multiples(T(x0 + double(f.d2[0])), sx2, cx2);
-        sincos_multiples(T(y0 + double(f.d2[1])), sy2, cy2);
-        T t1[4], t2[4];
-        third_derivs(p.S, sx1, cx1, sy1, cy1, t1);
-        third_derivs(p.S, sx2, cx2, sy2, cy2, t2);
+        // ---- parameter derivative, reverse mode through the trace
+        // seeds: Xbar = m (lambda_phi grad H + Hess H mu), Jbar[i][j] = m_i H_i lambda_j
         const T dtT = T(dt);
-        // the chain of the forward Jacobian: J1 = I - dt A0, B1 = A1 J1,
-        // J2 = I - dt (A0 + B1) / 4
+        const T Xb[2] = {T(m0 * (lf * double(Gr[0]) + double(Hs[0]) * mu0 + double(Hs[1]) * mu1)),
+                         T(m1 * (lf * double(Gr[1]) + double(Hs[2]) * mu0 + double(Hs[3]) * mu1))};
+        const T Jb[4] = {T(m0 * double(Gr[0]) * lx), T(m0 * double(Gr[0]) * ly),
+                         T(m1 * double(Gr[1]) * lx), T(m1 * double(Gr[1]) * ly)};
+        // forward chain pieces: J1 = I - dt A0, B1 = A1 J1, J2 = I - dt (A0 + B1) / 4
         T J1[4], B1[4], J2[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) J1[k] = T((k % 3) == 0) - dtT * f.A0[k];
@@ -195,65 +222,129 @@ __global__ __launch_bounds__(kBlock) void k_adjoint2d_stream(
 #pragma unroll
         for (int k = 0; k < 4; k++)
             J2[k] = T((k % 3) == 0) - dtT * (T(0.25) * f.A0[k] + T(0.25) * B1[k]);
+        // J = I - dt (A0/6 + B1/6 + 2 B2/3), B2 = A2 J2
+        T A0b[4], B1b[4], B2b[4], A1b[4], A2b[4], J1b[4], J2b[4];
 #pragma unroll
-        for (int m = 0; m < 4; m++)
+        for (int k = 0; k < 4; k++) {
+            A0b[k] = -dtT * T(1.0 / 6.0) * Jb[k];
+            B1b[k] = A0b[k];
+            B2b[k] = -dtT * T(2.0 / 3.0) * Jb[k];
+        }
+        mul2_abt(B2b, J2, A2b);
+        mul2_atb(f.A2, B2b, J2b);
 #pragma unroll
-            for (int n = 0; n < 4; n++) {
-                T vp[2], Gp[4];
-                // stage 1: v0' = c1 v_p(x), A0' = c1 G_p(x)
-                mode_field(m, n, sx0, cx0, sy0, cy0, vp, Gp);
-                T v0p[2] = {st.c1 * vp[0], st.c1 * vp[1]};
-                T A0p[4] = {st.c1 * Gp[0], st.c1 * Gp[1], st.c1 * Gp[2], st.c1 * Gp[3]};
-                const T x1p[2] = {-dtT * v0p[0], -dtT * v0p[1]};
-                // stage 2 at x1: v1' = c2 v_p(x1) + A1 x1', A1' = c2 (G_p(x1) + dG(x1) x1')
-                mode_field(m, n, sx1, cx1, sy1, cy1, vp, Gp);
-                T D[4];
-                grad_v_dir(t1, x1p[0], x1p[1], D);
-                const T v1p[2] = {st.c2 * vp[0] + f.A1[0] * x1p[0] + f.A1[1] * x1p[1],
-                                  st.c2 * vp[1] + f.A1[2] * x1p[0] + f.A1[3] * x1p[1]};
-                T A1p[4];
+        for (int k = 0; k < 4; k++) {
+            A0b[k] += -dtT * T(0.25) * J2b[k];
+            B1b[k] += -dtT * T(0.25) * J2b[k];
+        }
+        mul2_abt(B1b, J1, A1b);
+        mul2_atb(f.A1, B1b, J1b);
 #pragma unroll
-                for (int k = 0; k < 4; k++) A1p[k] = st.c2 * (Gp[k] + D[k]);
-                const T x2p[2] = {-dtT * (T(0.25) * v0p[0] + T(0.25) * v1p[0]),
-                                  -dtT * (T(0.25) * v0p[1] + T(0.25) * v1p[1])};
-                // stage 3 at x2
-                mode_field(m, n, sx2, cx2, sy2, cy2, vp, Gp);
-                grad_v_dir(t2, x2p[0], x2p[1], D);
-                const T v2p[2] = {st.c3 * vp[0] + f.A2[0] * x2p[0] + f.A2[1] * x2p[1],
-                                  st.c3 * vp[1] + f.A2[2] * x2p[0] + f.A2[3] * x2p[1]};
-                T A2p[4];
+        for (int k = 0; k < 4; k++) A0b[k] += -dtT * J1b[k];
+        // X = x - dt (v0/6 + v1/6 + 2 v2/3)
+        T v0b[2], v1b[2], v2b[2];
 #pragma unroll
-                for (int k = 0; k < 4; k++) A2p[k] = st.c3 * (Gp[k] + D[k]);
-                // foot: X' = -dt (v0'/6 + v1'/6 + 2 v2'/3)
-                T Xp[2];
+        for (int a = 0; a < 2; a++) {
+            v0b[a] = -dtT * T(1.0 / 6.0) * Xb[a];
+            v1b[a] = v0b[a];
+            v2b[a] = -dtT * T(2.0 / 3.0) * Xb[a];
+        }
+        const double x0 = g.lo[0] + double(i) * g.h[0], y0 = g.lo[1] + double(j) * g.h[1];
+        T sx[4], cx[4], sy[4], cy[4], t3[4];
+        T sb[16];
 #pragma unroll
-                for (int a = 0; a < 2; a++)
-                    Xp[a] = -dtT * (v0p[a] * T(1.0 / 6.0) + v1p[a] * T(1.0 / 6.0) +
-                                    v2p[a] * T(2.0 / 3.0));
-                // Jacobian: J1' = -dt A0', B1' = A1' J1 + A1 J1',
-                // J2' = -dt (A0' + B1')/4, B2' = A2' J2 + A2 J2',
-                // J' = -dt (A0'/6 + B1'/6 + 2 B2'/3)
-                T J1p[4], B1p[4], B1q[4], J2p[4], B2p[4], B2q[4];
+        for (int q = 0; q < 16; q++) sb[q] = T(0);
+        // stage 3 at x2 = x - dt (v0 + v1) / 4: v2 = c3 v(x2), A2 = c3 grad v(x2)
+        sincos_multiples(T(x0 + double(f.d2[0])), sx, cx);
+        sincos_multiples(T(y0 + double(f.d2[1])), sy, cy);
+        mode_terms(st.c3, v2b, A2b, sx, cx, sy, cy, sb);
+        third_derivs(p, sx, cx, sy, cy, t3);
+        {
+            T gx, gy;
+            grad_v_adj(t3, A2b, gx, gy);
+            const T x2b[2] = {f.A2[0] * v2b[0] + f.A2[2] * v2b[1] + st.c3 * gx,
+                              f.A2[1] * v2b[0] + f.A2[3] * v2b[1] + st.c3 * gy};
 #pragma unroll
-                for (int k = 0; k < 4; k++) J1p[k] = -dtT * A0p[k];
-                mul2(A1p, J1, B1p);
-                mul2(f.A1, J1p, B1q);
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    B1p[k] += B1q[k];
-                    J2p[k] = -dtT * (T(0.25) * A0p[k] + T(0.25) * B1p[k]);
-                }
-                mul2(A2p, J2, B2p);
-                mul2(f.A2, J2p, B2q);
-                double acc = r0 * m0 * double(Xp[0]) + r1 * m1 * double(Xp[1]);
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const T Jp = -dtT * (A0p[k] * T(1.0 / 6.0) + B1p[k] * T(1.0 / 6.0) +
-                                         (B2p[k] + B2q[k]) * T(2.0 / 3.0));
-                    acc += double(Jp) * P[k];
-                }
-                gacc[4 * m + n] += acc;
+            for (int a = 0; a < 2; a++) {
+                v0b[a] += -dtT * T(0.25) * x2b[a];
+                v1b[a] += -dtT * T(0.25) * x2b[a];
             }
+        }
+        // stage 2 at x1 = x - dt v0
+        sincos_multiples(T(x0 + double(f.d1[0])), sx, cx);
+        sincos_multiples(T(y0 + double(f.d1[1])), sy, cy);
+        mode_terms(st.c2, v1b, A1b, sx, cx, sy, cy, sb);
+        third_derivs(p, sx, cx, sy, cy, t3);
+        {
+            T gx, gy;
+            grad_v_adj(t3, A1b, gx, gy);
+            const T x1b[2] = {f.A1[0] * v1b[0] + f.A1[2] * v1b[1] + st.c2 * gx,
+                              f.A1[1] * v1b[0] + f.A1[3] * v1b[1] + st.c2 * gy};
+#pragma unroll
+            for (int a = 0; a < 2; a++) v0b[a] += -dtT * x1b[a];
+        }
+        // stage 1 at the node
+        sincos_multiples(T(x0), sx, cx);
+        sincos_multiples(T(y0), sy, cy);
+        mode_terms(st.c1, v0b, A0b, sx, cx, sy, cy, sb);
+#pragma unroll
+        for (int q = 0; q < 16; q++) gacc[q] += double(sb[q]);
+    }
+
+    // ---- scatter the cell data's share onto lam_out. The block's feet lie
+    // in a small box of cells (for moderate CFL numbers), so the block sums
+    // its contributions in an LDS tile first and adds the tile to lam_out
+    // with one global atomic per node and field: about 4x fewer global
+    // atomics. Boxes larger than the tile fall back to direct atomics.
+    __shared__ double s_tile[3 * kTileH * kTileW];
+    __shared__ int s_box[4];
+    if (threadIdx.x == 0) {
+        s_box[0] = s_box[2] = 0x7fffffff;
+        s_box[1] = s_box[3] = -0x7fffffff;
+    }
+    __syncthreads();
+    {
+        // min of cell0, -cell0, cell1, -cell1 over the block's nodes (the
+        // neutral element of min for lanes without a node)
+        int b[4] = {valid ? cell0 : 0x7fffffff, valid ? -cell0 : 0x7fffffff,
+                    valid ? cell1 : 0x7fffffff, valid ? -cell1 : 0x7fffffff};
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int k = 0; k < 4; k++) b[k] = min(b[k], __shfl_xor(b[k], off, 64));
+        if ((threadIdx.x & 63u) == 0) {
+            atomicMin(&s_box[0], b[0]);
+            atomicMax(&s_box[1], -b[1]);
+            atomicMin(&s_box[2], b[2]);
+            atomicMax(&s_box[3], -b[3]);
+        }
+    }
+    __syncthreads();
+    // the block has nodes: then all four are cell indices in [0, nc - 1]
+    const bool any = s_box[0] <= s_box[1] && s_box[2] <= s_box[3];
+    const int bx0 = s_box[0] - 1, by0 = s_box[2];
+    const int bw = any ? s_box[1] - s_box[0] + 4 : 0, bh = any ? s_box[3] - s_box[2] + 2 : 0;
+    const double inv2h = double(T(0.5 * g.inv_h[0]));
+    if (any && bw <= kTileW && bh <= kTileH) {
+        const int area = bw * bh;
+        for (int e = threadIdx.x; e < 3 * area; e += kBlock) s_tile[e] = 0.0;
+        __syncthreads();
+        if (valid)
+            emit_scatter<MIX>(dbar, cell0, cell1, g.nc[0], inv2h, [&](int fld, int x, int y, double v) {
+                atomicAdd(&s_tile[fld * area + (y - by0) * bw + (x - bx0)], v);
+            });
+        __syncthreads();
+        for (int e = threadIdx.x; e < 3 * area; e += kBlock) {
+            const double v = s_tile[e];
+            const int fld = e / area, r = e - fld * area;
+            const int y = by0 + r / bw, x = bx0 + r % bw;
+            if (v != 0.0 && x >= 0 && x < g.n[0] && y < g.n[1])
+                scatter(lam_out + fld * g.plane + int64_t(y) * g.pitch + x, v);
+        }
+    } else if (valid) {
+        emit_scatter<MIX>(dbar, cell0, cell1, g.nc[0], inv2h, [&](int fld, int x, int y, double v) {
+            scatter(lam_out + fld * g.plane + int64_t(y) * g.pitch + x, v);
+        });
     }
     block_reduce<16, true>(gacc, 0u, partials + int64_t(blockIdx.x) * 16);
 }
@@ -313,15 +404,21 @@ unsigned adjoint_blocks(const gals_ctx *ctx)
 
 template <typename T, int MIX>
 static void launch_adj(const gals_ctx *ctx, const Vel<T> &p, const void *phi, const void *grad,
-                       const double *lam_in, double *lam_out, double *partials, double dt,
+                       double *lam_in, double *lam_out, bool clear, double *partials, double dt,
                        double c1, double c2, double c3, const void *coltab, const void *rowtab,
                        hipStream_t s)
 {
     const Stage<T> st{T(c1), T(c2), T(c3)};
-    hipLaunchKernelGGL((k_adjoint2d_stream<T, MIX, sizeof(T) == 4>), dim3(adjoint_blocks(ctx)),
-                       dim3(kBlock), 0, s, ctx->g, p, st, dt, (const T *)coltab,
-                       (const T *)rowtab, (const T *)phi, (const T *)grad, lam_in, lam_out,
-                       partials);
+    if (clear)
+        hipLaunchKernelGGL((k_adjoint2d_stream<T, MIX, sizeof(T) == 4, true>),
+                           dim3(adjoint_blocks(ctx)), dim3(kBlock), 0, s, ctx->g, p, st, dt,
+                           (const T *)coltab, (const T *)rowtab, (const T *)phi, (const T *)grad,
+                           lam_in, lam_out, partials);
+    else
+        hipLaunchKernelGGL((k_adjoint2d_stream<T, MIX, sizeof(T) == 4, false>),
+                           dim3(adjoint_blocks(ctx)), dim3(kBlock), 0, s, ctx->g, p, st, dt,
+                           (const T *)coltab, (const T *)rowtab, (const T *)phi, (const T *)grad,
+                           lam_in, lam_out, partials);
 }
 
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s)
@@ -334,26 +431,25 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s)
 }
 
 hipError_t launch_adjoint_step(const gals_ctx *ctx, const void *phi, const void *grad,
-                               const double *lam_in, double *lam_out, double *partials,
+                               double *lam_in, double *lam_out, bool clear, double *partials,
                                double dt, double c1, double c2, double c3, const void *coltab,
                                const void *rowtab, hipStream_t s)
 {
-    hipError_t e = launch_zero(lam_out, 3 * ctx->g.plane, s);
-    if (e != hipSuccess) return e;
     if (ctx->prec == GALS_F32) {
         if (ctx->mixed == GALS_MIXED_ZERO)
-            launch_adj<float, GALS_MIXED_ZERO>(ctx, ctx->vf, phi, grad, lam_in, lam_out,
+            launch_adj<float, GALS_MIXED_ZERO>(ctx, ctx->vf, phi, grad, lam_in, lam_out, clear,
                                                partials, dt, c1, c2, c3, coltab, rowtab, s);
         else
-            launch_adj<float, GALS_MIXED_CENTRAL>(ctx, ctx->vf, phi, grad, lam_in, lam_out,
+            launch_adj<float, GALS_MIXED_CENTRAL>(ctx, ctx->vf, phi, grad, lam_in, lam_out, clear,
                                                   partials, dt, c1, c2, c3, coltab, rowtab, s);
     } else {
         if (ctx->mixed == GALS_MIXED_ZERO)
-            launch_adj<double, GALS_MIXED_ZERO>(ctx, ctx->vd, phi, grad, lam_in, lam_out,
+            launch_adj<double, GALS_MIXED_ZERO>(ctx, ctx->vd, phi, grad, lam_in, lam_out, clear,
                                                 partials, dt, c1, c2, c3, coltab, rowtab, s);
         else
             launch_adj<double, GALS_MIXED_CENTRAL>(ctx, ctx->vd, phi, grad, lam_in, lam_out,
-                                                   partials, dt, c1, c2, c3, coltab, rowtab, s);
+                                                   clear, partials, dt, c1, c2, c3, coltab,
+                                                   rowtab, s);
     }
     return hipGetLastError();
 }

@@ -596,6 +596,9 @@ int gals_adjoint(gals_ctx *ctx, const void *ckpt, size_t ckpt_bytes, double t0, 
     e = launch_tables(ctx, workspace, s);
     if (e == hipSuccess) e = launch_zero(part, int64_t(nblocks) * 16, s);
     if (e == hipSuccess) e = launch_zero(dS, 16, s);
+    // each adjoint step zeroes the buffer it reads, which then receives the
+    // next step's scatter: only the first target needs a fill
+    if (e == hipSuccess) e = launch_zero(lamB, 3 * ctx->g.plane, s);
     for (int64_t k = nsegments(steps, every) - 1; k >= 0 && e == hipSuccess; k--) {
         const int64_t n0 = k * every, len = n0 + every < steps ? every : steps - n0;
         // recompute the states of this segment from its checkpoint
@@ -613,7 +616,7 @@ int gals_adjoint(gals_ctx *ctx, const void *ckpt, size_t ckpt_bytes, double t0, 
         for (int64_t q = len - 1; q >= 0 && e == hipSuccess; q--) {
             const double t = t0 + double(n0 + q) * dt;
             const char *u = seg + size_t(q) * sb;
-            e = launch_adjoint_step(ctx, u, u + pb, lamA, lamB, part, dt,
+            e = launch_adjoint_step(ctx, u, u + pb, lamA, lamB, true, part, dt,
                                     time_factor(ctx->period, t + dt), time_factor(ctx->period, t),
                                     time_factor(ctx->period, t + 0.5 * dt), coltab, rowtab, s);
             double *tmp = lamA;
@@ -662,8 +665,9 @@ int gals_adjoint_step(gals_ctx *ctx, const void *phi, const void *grad, double t
     const int nblocks = int(adjoint_blocks(ctx));
     e = launch_tables(ctx, workspace, s);
     if (e == hipSuccess) e = launch_zero(part, int64_t(nblocks) * 16, s);
+    if (e == hipSuccess) e = launch_zero(lam_out, 3 * ctx->g.plane, s);
     if (e == hipSuccess)
-        e = launch_adjoint_step(ctx, phi, grad, lam_in, lam_out, part, dt,
+        e = launch_adjoint_step(ctx, phi, grad, const_cast<double *>(lam_in), lam_out, false, part, dt,
                                 time_factor(ctx->period, t + dt), time_factor(ctx->period, t),
                                 time_factor(ctx->period, t + 0.5 * dt), ws + coltab_offset(ctx),
                                 ws + rowtab_offset(ctx), s);

@@ -113,8 +113,9 @@ hipError_t launch_stream_tables(const gals_ctx *ctx, void *coltab, void *rowtab,
 // Adjoint of the stream-function step and the shape loss (adjoint.hip).
 // adjoint_blocks: blocks of the adjoint launch (16 partials each).
 unsigned adjoint_blocks(const gals_ctx *ctx);
+// lam_out must hold zeros; clear: zero lam_in as it is read.
 hipError_t launch_adjoint_step(const gals_ctx *ctx, const void *phi, const void *grad,
-                               const double *lam_in, double *lam_out, double *partials,
+                               double *lam_in, double *lam_out, bool clear, double *partials,
                                double dt, double c1, double c2, double c3, const void *coltab,
                                const void *rowtab, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
