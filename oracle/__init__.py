@@ -20,7 +20,8 @@ _LIB_PATH = os.path.join(_HERE, "libgals_oracle.so")
 # Velocity kinds (same numbering as the GPU library's public header; each side
 # defines its own copy).
 AFFINE, STREAM_SIN, VECPOT_SIN, VORTEX, PSEUDO1D, LEVEQUE3D = 1, 2, 3, 4, 5, 6
-MIXED_CENTRAL, MIXED_ZERO = 0, 2
+MIXED_CENTRAL, MIXED_CELL, MIXED_ZERO = 0, 1, 2
+PSI_SUPERCONSISTENT, PSI_HEUN = 0, 1
 BC_NEUMANN, BC_EXTRAPOLATE = 0, 1
 
 _lib = None
@@ -51,8 +52,8 @@ def _load():
     lib.orc_mixed.argtypes = [i, L, D, D, i, D, D]
     lib.orc_velocity.argtypes = [i, i, D, l, d, D, d, D, D]
     lib.orc_trace.argtypes = [i, i, D, l, d, D, d, d, D, D]
-    lib.orc_advance.argtypes = [i, L, D, D, i, D, l, d, i, i, D, D, d, d, l]
-    lib.orc_step_nodes.argtypes = [i, L, D, D, i, D, l, d, i, i, D, D, d, d, L, l, D, D]
+    lib.orc_advance.argtypes = [i, L, D, D, i, D, l, d, i, i, i, D, D, d, d, l]
+    lib.orc_step_nodes.argtypes = [i, L, D, D, i, D, l, d, i, i, i, D, D, d, d, L, l, D, D]
     lib.orc_eval_points.argtypes = [i, L, D, D, i, D, D, D, l, D, D, D, D, D]
     lib.orc_norms.argtypes = [i, L, D, D, D, D, D, D, d, d, D]
     lib.orc_max_speed.argtypes = [i, L, D, D, i, D, l, d, d]
@@ -138,20 +139,20 @@ def trace(dim, kind, params, period, x, t, dt):
 
 
 def advance(dim, ncell, lo, hi, kind, params, period, phi, psi, t0, dt, steps,
-            mixed_mode=MIXED_CENTRAL, bc=BC_NEUMANN):
+            mixed_mode=MIXED_CENTRAL, bc=BC_NEUMANN, psi_update=PSI_SUPERCONSISTENT):
     """Return (phi, psi) after ``steps`` steps; the inputs are not modified."""
     nc, lo, hi, ncp = _geom(ncell, lo, hi)
     p, npar = _params(params)
     phi = _f64(phi).copy()
     psi = _f64(psi).copy()
     _check(_load().orc_advance(dim, ncp, _dp(lo), _dp(hi), kind, _dp(p), npar, period,
-                               mixed_mode, bc, _dp(phi), _dp(psi), t0, dt, int(steps)),
-           "advance")
+                               mixed_mode, bc, psi_update, _dp(phi), _dp(psi), t0, dt,
+                               int(steps)), "advance")
     return phi, psi
 
 
 def step_nodes(dim, ncell, lo, hi, kind, params, period, phi, psi, t, dt, nodes,
-               mixed_mode=MIXED_CENTRAL, bc=BC_NEUMANN):
+               mixed_mode=MIXED_CENTRAL, bc=BC_NEUMANN, psi_update=PSI_SUPERCONSISTENT):
     """One step from t to t+dt at the given flat node indices."""
     nc, lo, hi, ncp = _geom(ncell, lo, hi)
     p, npar = _params(params)
@@ -161,7 +162,7 @@ def step_nodes(dim, ncell, lo, hi, kind, params, period, phi, psi, t, dt, nodes,
     po = np.zeros(cnt)
     go = np.zeros(cnt * dim)
     _check(_load().orc_step_nodes(dim, ncp, _dp(lo), _dp(hi), kind, _dp(p), npar, period,
-                                  mixed_mode, bc, _dp(phi), _dp(psi), t, dt,
+                                  mixed_mode, bc, psi_update, _dp(phi), _dp(psi), t, dt,
                                   nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), cnt,
                                   _dp(po), _dp(go)), "step_nodes")
     return po, go.reshape(cnt, dim)

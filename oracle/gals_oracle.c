@@ -9,10 +9,14 @@
  *   basis functions ........ sec. 2.3, eq. (1-cubic_basis_functions)
  *   Hermite interpolant .... sec. 2.3, eq. (p-cubic_interpolant), rectangular
  *                            cells scale the alpha-th datum by prod h_a^alpha_a
- *   cross derivatives ...... sec. 2.3, approach (A) central differencing
+ *   cross derivatives ...... sec. 2.3, approach (A) central differencing, or
+ *                            approach (B) cell-based (per cell, from the
+ *                            gradients at its own vertices)
  *   characteristic trace ... sec. 5.1, Ex. ex:superconsistent_ShuOsher
  *   one step ............... sec. 4 (steps 1-3) with the superconsistent
- *                            gradient update, eq. (superconsistency)
+ *                            gradient update, eq. (superconsistency), or the
+ *                            gradient ODE (eq. cir_evolution_psi) integrated
+ *                            along the characteristic by Heun's method
  *   normal, curvature ...... sec. 3.2, eqs. (surface_normal), (curvature)
  *   error norms ............ sec. 6.1, eq. (maximum_norm)
  *
@@ -20,6 +24,11 @@
  *   - cross derivatives at the first/last node use one-sided 3-point
  *     differences; phi_xy = D_x psi_y, phi_xz = D_x psi_z, phi_yz = D_y psi_z,
  *     phi_xyz = D_x D_y psi_z (the highest-index gradient component);
+ *   - approach (B) in 3D: a vertex takes phi_xy from the cell's xy facet
+ *     through it (likewise phi_xz, phi_yz), and phi_xyz from the first-order
+ *     formula on that xy facet;
+ *   - Heun's method for the gradient runs from the foot (time t, after the
+ *     boundary treatment) to the node (time t + dt), starting from grad H;
  *   - a foot outside the domain: with bc = 0 (homogeneous Neumann, as the
  *     paper prescribes at inflow edges in its tests, sec. 6.1 and 6.2) the
  *     foot is projected onto the domain and the extension, constant along
@@ -213,7 +222,8 @@ static int mixed_planes(const grid_t *g, int mode, const double *psi, double *mi
 {
     int nm = (g->dim == 2) ? 1 : 4;
     long N = g->nodes;
-    if (mode == 2) {
+    if (mode == 2 || mode == 1) {
+        /* zero (mode 2); cell-based values are formed per cell (mode 1) */
         memset(mixed, 0, sizeof(double) * (size_t)(nm * N));
         return 0;
     }
@@ -254,7 +264,7 @@ int orc_mixed(int dim, const long *ncell, const double *lo, const double *hi,
               int mode, const double *psi, double *mixed)
 {
     grid_t g;
-    if (make_grid(&g, dim, ncell, lo, hi) || !psi || !mixed) return -1;
+    if (make_grid(&g, dim, ncell, lo, hi) || !psi || !mixed || mode == 1) return -1;
     return mixed_planes(&g, mode, psi, mixed);
 }
 
@@ -478,6 +488,63 @@ static void locate(const grid_t *g, const double *X, long *cell, double *xi)
     }
 }
 
+/* Approach (B) on one facet: the cross derivative u_ab at the four facet
+ * vertices (index 0..3, bit 0 along axis a, bit 1 along axis b) from
+ * ga = phi_a and gb = phi_b there. Edge-centre differences
+ *   (ga(.,1) - ga(.,0)) / hb on the two edges along b,
+ *   (gb(1,.) - gb(0,.)) / ha on the two edges along a,
+ * then each vertex takes 3/4 of its two edges and -1/4 of the two others. */
+static void cell_cross(const double *ga, const double *gb, double ha, double hb, double *out)
+{
+    double ea[2], eb[2]; /* ea[k]: edge at position k along a; eb[k]: at k along b */
+    for (int k = 0; k < 2; k++) {
+        ea[k] = (ga[k + 2] - ga[k]) / hb;
+        eb[k] = (gb[2 * k + 1] - gb[2 * k]) / ha;
+    }
+    for (int v = 0; v < 4; v++) {
+        int va = v & 1, vb = (v >> 1) & 1;
+        out[v] = 0.75 * (ea[va] + eb[vb]) - 0.25 * (ea[1 - va] + eb[1 - vb]);
+    }
+}
+
+/* Replace the cross derivatives of gathered cell data by approach (B). */
+static void cell_based_cross(const grid_t *g, double *data)
+{
+    int nv = 1 << g->dim;
+    if (g->dim == 2) {
+        double ga[4], gb[4], out[4];
+        for (int v = 0; v < 4; v++) { ga[v] = data[v * 4 + 1]; gb[v] = data[v * 4 + 2]; }
+        cell_cross(ga, gb, g->h[0], g->h[1], out);
+        for (int v = 0; v < 4; v++) data[v * 4 + 3] = out[v];
+        return;
+    }
+    /* 3D: the facet through vertex v normal to axis c, for the pair (a, b) */
+    static const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2}, pc[3] = {2, 1, 0};
+    static const int slot[3] = {3, 5, 6}; /* xy, xz, yz */
+    for (int q = 0; q < 3; q++) {
+        int a = pa[q], b = pb[q], c = pc[q];
+        for (int lc = 0; lc < 2; lc++) {
+            double ga[4], gb[4], out[4];
+            int ids[4];
+            for (int k = 0; k < 4; k++) {
+                int v = ((k & 1) << a) | (((k >> 1) & 1) << b) | (lc << c);
+                ids[k] = v;
+                ga[k] = data[v * nv + (1 << a)];
+                gb[k] = data[v * nv + (1 << b)];
+            }
+            cell_cross(ga, gb, g->h[a], g->h[b], out);
+            for (int k = 0; k < 4; k++) data[ids[k] * nv + slot[q]] = out[k];
+        }
+    }
+    /* phi_xyz (first order) from psi_z on the xy facet at each z level */
+    for (int lz = 0; lz < 2; lz++) {
+        int v00 = 4 * lz, v10 = v00 + 1, v01 = v00 + 2, v11 = v00 + 3;
+        double val = (data[v11 * nv + 4] - data[v01 * nv + 4] - data[v10 * nv + 4] +
+                      data[v00 * nv + 4]) / (g->h[0] * g->h[1]);
+        for (int k = 0; k < 4; k++) data[(v00 + k) * nv + 7] = val;
+    }
+}
+
 /* Gather the 4^p data of a cell: data[v*2^p + alpha]. */
 static void gather_cell(const grid_t *g, const long *cell, const double *phi,
                         const double *psi, const double *mixed, double *data)
@@ -507,9 +574,9 @@ static void gather_cell(const grid_t *g, const long *cell, const double *phi,
 /* One GA-CIR step at node idx (sec. 4, steps 1-3, with the superconsistent
  * gradient update of eq. superconsistency). */
 static int step_node(const grid_t *g, int kind, const double *params, long np,
-                     double period, int bc, const double *phi, const double *psi,
-                     const double *mixed, double t, double dt, long idx,
-                     double *phi_new, double *psi_new)
+                     double period, int bc, int mixed_mode, int psi_update,
+                     const double *phi, const double *psi, const double *mixed, double t,
+                     double dt, long idx, double *phi_new, double *psi_new)
 {
     int d = g->dim;
     long ijk[MAXD], cell[MAXD];
@@ -528,10 +595,31 @@ static int step_node(const grid_t *g, int kind, const double *params, long np,
     }
     locate(g, X, cell, xi);
     gather_cell(g, cell, phi, psi, mixed, data);
+    if (mixed_mode == 1) cell_based_cross(g, data);
     orc_hermite(d, data, g->h, xi, &val, grad, NULL);
     for (int a = 0; a < d; a++)
         if (outside[a]) grad[a] = 0.0; /* the extension is constant along the normal */
     *phi_new = val;
+    if (psi_update == 1) {
+        /* Heun's method for d psi/d tau = -grad v . psi (eq. cir_evolution_psi)
+         * from the foot at time t to the node at time t + dt */
+        double v[MAXD], Gf[9], Gn[9], k1[MAXD], k2[MAXD], pp[MAXD];
+        if (orc_velocity(d, kind, params, np, period, X, t, v, Gf)) return -1;
+        if (orc_velocity(d, kind, params, np, period, x, t + dt, v, Gn)) return -1;
+        for (int i = 0; i < d; i++) {
+            double s = 0.0;
+            for (int j = 0; j < d; j++) s += Gf[i * d + j] * grad[j];
+            k1[i] = -s;
+        }
+        for (int i = 0; i < d; i++) pp[i] = grad[i] + dt * k1[i];
+        for (int i = 0; i < d; i++) {
+            double s = 0.0;
+            for (int j = 0; j < d; j++) s += Gn[i * d + j] * pp[j];
+            k2[i] = -s;
+        }
+        for (int i = 0; i < d; i++) psi_new[i] = grad[i] + 0.5 * dt * (k1[i] + k2[i]);
+        return 0;
+    }
     for (int i = 0; i < d; i++) {
         double s = 0.0;
         for (int j = 0; j < d; j++) s += D[i * d + j] * grad[j];
@@ -542,11 +630,12 @@ static int step_node(const grid_t *g, int kind, const double *params, long np,
 
 int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
                 int kind, const double *params, long nparams, double period,
-                int mixed_mode, int bc, double *phi, double *psi,
+                int mixed_mode, int bc, int psi_update, double *phi, double *psi,
                 double t0, double dt, long steps)
 {
     grid_t g;
-    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || steps < 0 || bc < 0 || bc > 1)
+    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || steps < 0 || bc < 0 || bc > 1 ||
+        psi_update < 0 || psi_update > 1)
         return -1;
     long N = g.nodes;
     int nm = (dim == 2) ? 1 : 4;
@@ -561,8 +650,8 @@ int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
 #pragma omp parallel for schedule(static) reduction(| : bad)
         for (long idx = 0; idx < N; idx++) {
             double pn, gn[MAXD];
-            if (step_node(&g, kind, params, nparams, period, bc, phi, psi, mixed, t, dt,
-                          idx, &pn, gn)) {
+            if (step_node(&g, kind, params, nparams, period, bc, mixed_mode, psi_update, phi,
+                          psi, mixed, t, dt, idx, &pn, gn)) {
                 bad = 1;
                 continue;
             }
@@ -579,13 +668,13 @@ int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
 
 int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *hi,
                    int kind, const double *params, long nparams, double period,
-                   int mixed_mode, int bc, const double *phi, const double *psi,
-                   double t, double dt, const long *nodes, long count,
+                   int mixed_mode, int bc, int psi_update, const double *phi,
+                   const double *psi, double t, double dt, const long *nodes, long count,
                    double *phi_out, double *psi_out)
 {
     grid_t g;
     if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || !nodes || count < 0 ||
-        bc < 0 || bc > 1)
+        bc < 0 || bc > 1 || psi_update < 0 || psi_update > 1)
         return -1;
     long N = g.nodes;
     int nm = (dim == 2) ? 1 : 4;
@@ -594,8 +683,8 @@ int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *h
     int err = mixed_planes(&g, mixed_mode, psi, mixed);
     for (long k = 0; k < count && !err; k++) {
         if (nodes[k] < 0 || nodes[k] >= N) { err = -1; break; }
-        err = step_node(&g, kind, params, nparams, period, bc, phi, psi, mixed, t, dt,
-                        nodes[k], &phi_out[k], &psi_out[k * dim]);
+        err = step_node(&g, kind, params, nparams, period, bc, mixed_mode, psi_update, phi,
+                        psi, mixed, t, dt, nodes[k], &phi_out[k], &psi_out[k * dim]);
     }
     free(mixed);
     return err;
@@ -624,6 +713,7 @@ int orc_eval_points(int dim, const long *ncell, const double *lo, const double *
         double xi[MAXD], data[64], H, Gr[MAXD], Hs[9];
         locate(&g, pts + p * dim, cell, xi);
         gather_cell(&g, cell, phi, psi, mixed, data);
+        if (mixed_mode == 1) cell_based_cross(&g, data);
         orc_hermite(dim, data, g.h, xi, &H, Gr, Hs);
         if (val) val[p] = H;
         if (grad) for (int a = 0; a < dim; a++) grad[p * dim + a] = Gr[a];

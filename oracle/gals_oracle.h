@@ -58,7 +58,9 @@ int orc_hermite(int dim, const double *data, const double *h, const double *xi,
 
 /* Cross derivatives at every node from psi (sec. 2.3). mode 0: central (A)
  * with one-sided 3-point differences at the first and last node; mode 2: zero.
- * Output planes: 2D [phi_xy]; 3D [phi_xy, phi_xz, phi_yz, phi_xyz]. */
+ * Output planes: 2D [phi_xy]; 3D [phi_xy, phi_xz, phi_yz, phi_xyz]. Mode 1,
+ * the cell-based approach (B), has no per-node values (-1 here); the step,
+ * the evaluation and orc_grad_cs form them per cell. */
 int orc_mixed(int dim, const long *ncell, const double *lo, const double *hi,
               int mode, const double *psi, double *mixed);
 
@@ -74,18 +76,20 @@ int orc_trace(int dim, int kind, const double *params, long nparams, double peri
               const double *x, double t, double dt, double *X, double *D);
 
 /* Advance phi, psi in place by `steps` GA-CIR steps of size dt from time t0.
- * Step n goes from t0 + n dt to t0 + (n+1) dt. */
+ * Step n goes from t0 + n dt to t0 + (n+1) dt. mixed_mode 0 (A), 1 (B),
+ * 2 zero; psi_update 0 superconsistent (eq. superconsistency), 1 Heun's
+ * method for eq. cir_evolution_psi along the characteristic. */
 int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
                 int kind, const double *params, long nparams, double period,
-                int mixed_mode, int bc, double *phi, double *psi,
+                int mixed_mode, int bc, int psi_update, double *phi, double *psi,
                 double t0, double dt, long steps);
 
 /* One step from time t to t+dt, evaluated only at the listed node indices.
  * phi_out[count], psi_out[count*dim]. */
 int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *hi,
                    int kind, const double *params, long nparams, double period,
-                   int mixed_mode, int bc, const double *phi, const double *psi,
-                   double t, double dt, const long *nodes, long count,
+                   int mixed_mode, int bc, int psi_update, const double *phi,
+                   const double *psi, double t, double dt, const long *nodes, long count,
                    double *phi_out, double *psi_out);
 
 /* Value, gradient, Hessian, normal and curvature of the Hermite interpolant at

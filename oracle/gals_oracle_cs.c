@@ -14,11 +14,12 @@
  * step is evaluated in complex arithmetic exactly as the paper states it
  * (sec. 4 steps 1-3, the superconsistent trace of Ex.
  * ex:superconsistent_ShuOsher, the Hermite interpolant of eq.
- * p-cubic_interpolant, the cross derivatives of approach (A), sec. 2.3); the
- * only non-analytic operations are the cell choice and the boundary test,
- * which look at the real part, so the result is the derivative of the
- * discrete advance with its cells held fixed (the advance is C^1 in S: the
- * interpolant is C^1 across cell faces).
+ * p-cubic_interpolant, the cross derivatives of approach (A) or (B), sec.
+ * 2.3); the only non-analytic operations are the cell choice and the boundary
+ * test, which look at the real part, so the result is the derivative of the
+ * discrete advance with its cells held fixed (with (A) the advance is C^1 in
+ * S, the interpolant being C^1 across cell faces; with (B) it is C^1 except
+ * where a foot crosses a face).
  *
  * Two functionals:
  *   linear:  F = sum over nodes of lam_phi phi_T + lam_x psi_x,T + lam_y psi_y,T
@@ -172,6 +173,22 @@ static cplx diff_x_cs(const grid2_t *g, const cplx *u, long i, long j)
     return (u[r + i + 1] - u[r + i - 1]) / (2.0 * h);
 }
 
+/* Approach (B) (sec. 2.3) on the cell's data: edge-centre differences of
+ * psi_x along y and psi_y along x, then 3/4 of a vertex's two edges and -1/4
+ * of the two others. */
+static void cell_cross_cs(cplx *data, double hx, double hy)
+{
+    cplx ex[2], ey[2];
+    for (int k = 0; k < 2; k++) {
+        ex[k] = (data[(k + 2) * 4 + 1] - data[k * 4 + 1]) / hy;
+        ey[k] = (data[(2 * k + 1) * 4 + 2] - data[(2 * k) * 4 + 2]) / hx;
+    }
+    for (int v = 0; v < 4; v++) {
+        int vx = v & 1, vy = v >> 1;
+        data[v * 4 + 3] = 0.75 * (ex[vx] + ey[vy]) - 0.25 * (ex[1 - vx] + ey[1 - vy]);
+    }
+}
+
 static void step_cs(const grid2_t *g, const double *params, long nmodes, int pm, int pn,
                     double period, int mixed_mode, int bc, const cplx *phi, const cplx *psi,
                     cplx *mixed, double t, double dt, cplx *phi2, cplx *psi2)
@@ -181,7 +198,7 @@ static void step_cs(const grid2_t *g, const double *params, long nmodes, int pm,
 #pragma omp parallel for schedule(static)
     for (long idx = 0; idx < N; idx++) {
         long i = idx % g->nn[0], j = idx / g->nn[0];
-        mixed[idx] = (mixed_mode == 0) ? diff_x_cs(g, psi_y, i, j) : 0.0; /* phi_xy = D_x psi_y */
+        mixed[idx] = (mixed_mode == 0) ? diff_x_cs(g, psi_y, i, j) : 0.0; /* phi_xy = D_x psi_y (A) */
     }
 #pragma omp parallel for schedule(static)
     for (long idx = 0; idx < N; idx++) {
@@ -216,6 +233,7 @@ static void step_cs(const grid2_t *g, const double *params, long nmodes, int pm,
             data[v * 4 + 2] = psi[N + k];
             data[v * 4 + 3] = mixed[k];
         }
+        if (mixed_mode == 1) cell_cross_cs(data, g->h[0], g->h[1]);
         int d00[2] = {0, 0}, d10[2] = {1, 0}, d01[2] = {0, 1};
         phi2[idx] = hermite_cs(data, g->h, xi, d00);
         grad[0] = outside[0] ? 0.0 : hermite_cs(data, g->h, xi, d10);
@@ -239,7 +257,7 @@ int orc_grad_cs(const long *ncell, const double *lo, const double *hi, const dou
 {
     grid2_t g;
     if (!ncell || !lo || !hi || !params || nparams % 3 || !phi0 || !psi0 || steps < 0 ||
-        !grad || (!lam && !phi_target) || (mixed_mode != 0 && mixed_mode != 2) || bc < 0 ||
+        !grad || (!lam && !phi_target) || mixed_mode < 0 || mixed_mode > 2 || bc < 0 ||
         bc > 1)
         return -1;
     g.N = 1;
