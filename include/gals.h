@@ -57,9 +57,19 @@ enum { GALS_OK = 0, GALS_EINVAL = -1, GALS_ENOMEM = -2, GALS_EHIP = -3, GALS_ENO
 enum { GALS_F32 = 1, GALS_F64 = 2 };
 
 /* Cross-derivative reconstruction (sec. 2.3): central differencing (A), with
- * one-sided 3-point differences at the first and last node; or all zero (the
+ * one-sided 3-point differences at the first and last node; the cell-based
+ * approach (B), from the gradients at the cell's own vertices (edge-centre
+ * differences weighted 3/4, 3/4, -1/4, -1/4; in 3D on the facet through the
+ * vertex, and the first-order phi_xyz on the xy facet), which leaves the
+ * interpolant continuous with O(h^3) gradient jumps; or all zero (the
  * robustness ablation noted at the end of sec. 2.3). */
-enum { GALS_MIXED_CENTRAL = 0, GALS_MIXED_ZERO = 2 };
+enum { GALS_MIXED_CENTRAL = 0, GALS_MIXED_CELL = 1, GALS_MIXED_ZERO = 2 };
+
+/* Gradient update (sec. 4 step 3): the superconsistent update psi_new =
+ * grad(foot map)^T grad H (eq. superconsistency, the default), or Heun's
+ * method for eq. cir_evolution_psi along the characteristic, from grad H at
+ * the foot (time t) to the node (time t + dt), with grad v at both ends. */
+enum { GALS_PSI_SUPERCONSISTENT = 0, GALS_PSI_HEUN = 1 };
 
 /* Treatment of a departure point (foot) outside the domain. GALS_BC_NEUMANN
  * (the default): homogeneous Neumann, the boundary condition the paper
@@ -129,6 +139,9 @@ int gals_workspace_bytes(const gals_ctx *ctx, size_t *bytes);
  * ENOTSUP on sine-mode indices outside 1..4 or too many modes. Host-only. */
 int gals_set_velocity(gals_ctx *ctx, int kind, const double *params, int64_t nparams,
                       double period);
+/* Gradient update of later advances: GALS_PSI_SUPERCONSISTENT (default) or
+ * GALS_PSI_HEUN. Batches and the adjoint use the superconsistent update. */
+int gals_set_psi_update(gals_ctx *ctx, int mode);
 
 /* Advance phi and grad (device, in place) by `steps` GA-CIR steps of size dt
  * from time t0 (sec. 4, steps 1-3, with the superconsistent update of eq.

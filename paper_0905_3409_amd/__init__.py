@@ -25,7 +25,8 @@ LIB_PATH = os.path.join(_HERE, "libgals.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSUP = 0, -1, -2, -3, -4
 F32, F64 = 1, 2
-MIXED_CENTRAL, MIXED_ZERO = 0, 2
+MIXED_CENTRAL, MIXED_CELL, MIXED_ZERO = 0, 1, 2
+PSI_SUPERCONSISTENT, PSI_HEUN = 0, 1
 BC_NEUMANN, BC_EXTRAPOLATE = 0, 1
 AFFINE, STREAM_SIN, VECPOT_SIN, VORTEX, PSEUDO1D, LEVEQUE3D = 1, 2, 3, 4, 5, 6
 
@@ -36,7 +37,7 @@ EXPORTS = ("gals_create", "gals_destroy", "gals_layout", "gals_workspace_bytes",
            "gals_batch_set_tiles", "gals_batch_get_tiles", "gals_batch_advance",
            "gals_batch_autotune", "gals_checkpoint_bytes", "gals_advance_save",
            "gals_adjoint_workspace_bytes", "gals_adjoint", "gals_adjoint_step",
-           "gals_shape_loss")
+           "gals_shape_loss", "gals_set_psi_update")
 
 _lib = None
 
@@ -83,6 +84,7 @@ def lib():
     L.gals_adjoint.argtypes = [vp, vp, sz, d, d, i64, i64, vp, vp, vp, sz, vp]
     L.gals_adjoint_step.argtypes = [vp, vp, vp, d, d, vp, vp, vp, vp, sz, vp]
     L.gals_shape_loss.argtypes = [vp, vp, vp, d, PD, vp, vp, sz, vp]
+    L.gals_set_psi_update.argtypes = [vp, i]
     L.gals_last_error.argtypes = []
     L.gals_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -206,6 +208,10 @@ class Grid:
         p = np.ascontiguousarray(params, dtype=np.float64)
         ptr = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if p.size else None
         check(lib().gals_set_velocity(self._ctx, int(kind), ptr, p.size, float(period)))
+
+    def set_psi_update(self, mode):
+        """PSI_SUPERCONSISTENT (default) or PSI_HEUN for later advances."""
+        check(lib().gals_set_psi_update(self._ctx, int(mode)))
 
     def advance(self, state, t0, dt, steps, stream=None):
         """Advance the state in place (asynchronous on the stream)."""

@@ -206,6 +206,29 @@ __global__ __launch_bounds__(kBlock) void k_adjoint2d_stream(
                              mu0 * double(bx.dw[kx]) * double(by.w[ky]) +
                              mu1 * double(bx.w[kx]) * double(by.dw[ky]);
             }
+        if constexpr (MIX == GALS_MIXED_CELL) {
+            // transpose of approach (B): phi_xy[v] = 3/4 (ea[vx] + eb[vy])
+            // - 1/4 (ea[1-vx] + eb[1-vy]) with ea[k] = (psi_x[k+2] - psi_x[k]) / hy
+            // and eb[k] = (psi_y[2k+1] - psi_y[2k]) / hx, all within the cell
+            const double ihx = double(T(g.inv_h[0])), ihy = double(T(g.inv_h[1]));
+            double ea[2] = {0.0, 0.0}, eb[2] = {0.0, 0.0};
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int vx = v & 1, vy = v >> 1;
+                ea[vx] += 0.75 * dbar[v][3];
+                ea[1 - vx] -= 0.25 * dbar[v][3];
+                eb[vy] += 0.75 * dbar[v][3];
+                eb[1 - vy] -= 0.25 * dbar[v][3];
+                dbar[v][3] = 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                dbar[k + 2][1] += ea[k] * ihy;
+                dbar[k][1] -= ea[k] * ihy;
+                dbar[2 * k + 1][2] += eb[k] * ihx;
+                dbar[2 * k][2] -= eb[k] * ihx;
+            }
+        }
 
         // ---- parameter derivative, reverse mode through the trace
         // seeds: Xbar = m (lambda_phi grad H + Hess H mu), Jbar[i][j] = m_i H_i lambda_j
@@ -435,22 +458,19 @@ hipError_t launch_adjoint_step(const gals_ctx *ctx, const void *phi, const void 
                                double dt, double c1, double c2, double c3, const void *coltab,
                                const void *rowtab, hipStream_t s)
 {
+#define GALS_ADJ(T, V, M)                                                                   \
+    launch_adj<T, M>(ctx, ctx->V, phi, grad, lam_in, lam_out, clear, partials, dt, c1, c2, c3, \
+                     coltab, rowtab, s)
     if (ctx->prec == GALS_F32) {
-        if (ctx->mixed == GALS_MIXED_ZERO)
-            launch_adj<float, GALS_MIXED_ZERO>(ctx, ctx->vf, phi, grad, lam_in, lam_out, clear,
-                                               partials, dt, c1, c2, c3, coltab, rowtab, s);
-        else
-            launch_adj<float, GALS_MIXED_CENTRAL>(ctx, ctx->vf, phi, grad, lam_in, lam_out, clear,
-                                                  partials, dt, c1, c2, c3, coltab, rowtab, s);
+        if (ctx->mixed == GALS_MIXED_ZERO) GALS_ADJ(float, vf, GALS_MIXED_ZERO);
+        else if (ctx->mixed == GALS_MIXED_CELL) GALS_ADJ(float, vf, GALS_MIXED_CELL);
+        else GALS_ADJ(float, vf, GALS_MIXED_CENTRAL);
     } else {
-        if (ctx->mixed == GALS_MIXED_ZERO)
-            launch_adj<double, GALS_MIXED_ZERO>(ctx, ctx->vd, phi, grad, lam_in, lam_out, clear,
-                                                partials, dt, c1, c2, c3, coltab, rowtab, s);
-        else
-            launch_adj<double, GALS_MIXED_CENTRAL>(ctx, ctx->vd, phi, grad, lam_in, lam_out,
-                                                   clear, partials, dt, c1, c2, c3, coltab,
-                                                   rowtab, s);
+        if (ctx->mixed == GALS_MIXED_ZERO) GALS_ADJ(double, vd, GALS_MIXED_ZERO);
+        else if (ctx->mixed == GALS_MIXED_CELL) GALS_ADJ(double, vd, GALS_MIXED_CELL);
+        else GALS_ADJ(double, vd, GALS_MIXED_CENTRAL);
     }
+#undef GALS_ADJ
     return hipGetLastError();
 }
 

@@ -148,15 +148,17 @@ hipError_t launch_batch_step(int prec, int mixed, const void *probs, const TileR
 {
     if (prec == GALS_F32) {
         const Stage<float> st{float(c1), float(c2), float(c3)};
-        auto kern = mixed == GALS_MIXED_ZERO ? k_batch_step<float, GALS_MIXED_ZERO, true>
-                                             : k_batch_step<float, GALS_MIXED_CENTRAL, true>;
+        auto kern = mixed == GALS_MIXED_ZERO   ? k_batch_step<float, GALS_MIXED_ZERO, true>
+                    : mixed == GALS_MIXED_CELL ? k_batch_step<float, GALS_MIXED_CELL, true>
+                                               : k_batch_step<float, GALS_MIXED_CENTRAL, true>;
         hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s,
                            (const BatchProb<float> *)probs, tiles, ntiles, st, dt,
                            (const float *)tab, (const float *)in, (float *)out);
     } else {
         const Stage<double> st{c1, c2, c3};
-        auto kern = mixed == GALS_MIXED_ZERO ? k_batch_step<double, GALS_MIXED_ZERO, false>
-                                             : k_batch_step<double, GALS_MIXED_CENTRAL, false>;
+        auto kern = mixed == GALS_MIXED_ZERO   ? k_batch_step<double, GALS_MIXED_ZERO, false>
+                    : mixed == GALS_MIXED_CELL ? k_batch_step<double, GALS_MIXED_CELL, false>
+                                               : k_batch_step<double, GALS_MIXED_CENTRAL, false>;
         hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s,
                            (const BatchProb<double> *)probs, tiles, ntiles, st, dt,
                            (const double *)tab, (const double *)in, (double *)out);

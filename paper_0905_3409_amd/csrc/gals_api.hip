@@ -194,7 +194,8 @@ int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo,
     if (!ncell || !lo || !hi) return fail(GALS_EINVAL, "gals_create: NULL ncell/lo/hi");
     if (prec != GALS_F32 && prec != GALS_F64)
         return fail(GALS_EINVAL, "gals_create: unknown precision %d", prec);
-    if (mixed_mode != GALS_MIXED_CENTRAL && mixed_mode != GALS_MIXED_ZERO)
+    if (mixed_mode != GALS_MIXED_CENTRAL && mixed_mode != GALS_MIXED_CELL &&
+        mixed_mode != GALS_MIXED_ZERO)
         return fail(GALS_EINVAL, "gals_create: unknown mixed-derivative mode %d", mixed_mode);
     if (bc != GALS_BC_NEUMANN && bc != GALS_BC_EXTRAPOLATE)
         return fail(GALS_EINVAL, "gals_create: unknown boundary treatment %d", bc);
@@ -326,6 +327,15 @@ int gals_set_velocity(gals_ctx *ctx, int kind, const double *params, int64_t npa
     fill_vel(ctx->vf, kind, d, params, nparams);
     fill_vel(ctx->vd, kind, d, params, nparams);
     ctx->vel_set = true;
+    return GALS_OK;
+}
+
+int gals_set_psi_update(gals_ctx *ctx, int mode)
+{
+    if (!ctx) return fail(GALS_EINVAL, "gals_set_psi_update: NULL context");
+    if (mode != GALS_PSI_SUPERCONSISTENT && mode != GALS_PSI_HEUN)
+        return fail(GALS_EINVAL, "gals_set_psi_update: unknown mode %d", mode);
+    ctx->psi = mode;
     return GALS_OK;
 }
 
@@ -480,6 +490,9 @@ int check_adjoint_ctx(const gals_ctx *ctx, const char *what)
     if (!ctx->vel_set) return fail(GALS_EINVAL, "%s: no velocity set", what);
     if (ctx->dim != 2 || ctx->vel_kind != GALS_VEL_STREAM_SIN)
         return fail(GALS_ENOTSUP, "%s: the adjoint covers 2D GALS_VEL_STREAM_SIN fields", what);
+    if (ctx->psi != GALS_PSI_SUPERCONSISTENT)
+        return fail(GALS_ENOTSUP, "%s: the adjoint covers the superconsistent gradient update",
+                    what);
     return GALS_OK;
 }
 

@@ -250,7 +250,8 @@ int gals_batch_create(gals_batch **out, int64_t nprob, const int64_t *ncell, con
     if (nprob < 1 || nprob > 65535) return bfail(GALS_EINVAL, "gals_batch_create: nprob must be 1..65535");
     if (!ncell || !lo || !hi) return bfail(GALS_EINVAL, "gals_batch_create: NULL ncell/lo/hi");
     if (prec != GALS_F32 && prec != GALS_F64) return bfail(GALS_EINVAL, "gals_batch_create: precision");
-    if (mixed_mode != GALS_MIXED_CENTRAL && mixed_mode != GALS_MIXED_ZERO)
+    if (mixed_mode != GALS_MIXED_CENTRAL && mixed_mode != GALS_MIXED_CELL &&
+        mixed_mode != GALS_MIXED_ZERO)
         return bfail(GALS_EINVAL, "gals_batch_create: mixed-derivative mode");
     if (bc != GALS_BC_NEUMANN && bc != GALS_BC_EXTRAPOLATE)
         return bfail(GALS_EINVAL, "gals_batch_create: boundary treatment");

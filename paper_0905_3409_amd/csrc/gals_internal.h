@@ -89,6 +89,7 @@ struct gals_ctx {
     int dim;
     int prec;
     int mixed;
+    int psi;  // GALS_PSI_*
     int device;
     gals::Geom g;
     bool vel_set;

@@ -48,7 +48,9 @@ __device__ __forceinline__ void jacobian_chain(const T *A0, const T *A1, const T
                dtT * (A0[k] * T(1.0 / 6.0) + B1[k] * T(1.0 / 6.0) + B2[k] * T(2.0 / 3.0));
 }
 
-template <typename T, int D, int KIND>
+// CHAIN = false (Heun's gradient update) skips the Jacobian chain; J then
+// receives A0, the velocity Jacobian at the node at time t + dt.
+template <typename T, int D, int KIND, bool CHAIN = true>
 __device__ __forceinline__ void trace(const Vel<T> &p, const Stage<T> &st, double dt,
                                       const double *x, double *X, T *J)
 {
@@ -69,7 +71,38 @@ __device__ __forceinline__ void trace(const Vel<T> &p, const Stage<T> &st, doubl
     for (int i = 0; i < D; i++)
         X[i] = x[i] - dt * (double(v0[i]) * (1.0 / 6.0) + double(v1[i]) * (1.0 / 6.0) +
                             double(v2[i]) * (2.0 / 3.0));
-    jacobian_chain<T, D>(A0, A1, A2, dtT, J);
+    if constexpr (CHAIN) {
+        jacobian_chain<T, D>(A0, A1, A2, dtT, J);
+    } else {
+#pragma unroll
+        for (int k = 0; k < D * D; k++) J[k] = A0[k];
+    }
+}
+
+// Heun's method for d psi/d tau = -grad v . psi (eq. cir_evolution_psi)
+// from the foot (time t, velocity Jacobian Af) to the node (time t + dt,
+// An), J form (A[i][j] = dv_i/dx_j, so grad v . psi = A^T psi):
+// k1 = -Af^T g, k2 = -An^T (g + dt k1), psi = g + dt (k1 + k2) / 2.
+template <typename T, int D>
+__device__ __forceinline__ void heun_gradient(const T *Af, const T *An, T dtT, const T *g, T *psi)
+{
+    T k1[D], pp[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        T s = Af[i] * g[0];
+#pragma unroll
+        for (int j = 1; j < D; j++) s += Af[j * D + i] * g[j];
+        k1[i] = -s;
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) pp[i] = g[i] + dtT * k1[i];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        T s = An[i] * pp[0];
+#pragma unroll
+        for (int j = 1; j < D; j++) s += An[j * D + i] * pp[j];
+        psi[i] = g[i] + T(0.5) * dtT * (k1[i] - s);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -154,6 +187,22 @@ __device__ __forceinline__ void diff_pair(const T *u, bool lo_edge, bool hi_edge
     d1 = (hi_edge ? (T(3) * u[2] - T(4) * u[1] + u[0]) : (u[3] - u[1])) * inv2h;
 }
 
+// Cross derivative by the cell-based approach (B) (sec. 2.3) on one cell
+// facet spanned by axes a, b: ga = phi_a, gb = phi_b at the facet's vertices
+// (index bit 0 along a, bit 1 along b). Differences along the four edges
+// give the cross derivative at the edge centres; a vertex takes 3/4 of its
+// two edges and -1/4 of the two opposite ones (bilinear extrapolation).
+template <typename T>
+__device__ __forceinline__ void cell_cross(const T *ga, const T *gb, T inv_ha, T inv_hb, T *out)
+{
+    const T ea0 = (ga[2] - ga[0]) * inv_hb, ea1 = (ga[3] - ga[1]) * inv_hb;  // edges along b
+    const T eb0 = (gb[1] - gb[0]) * inv_ha, eb1 = (gb[3] - gb[2]) * inv_ha;  // edges along a
+    out[0] = T(0.75) * (ea0 + eb0) - T(0.25) * (ea1 + eb1);
+    out[1] = T(0.75) * (ea1 + eb0) - T(0.25) * (ea0 + eb1);
+    out[2] = T(0.75) * (ea0 + eb1) - T(0.25) * (ea1 + eb0);
+    out[3] = T(0.75) * (ea1 + eb1) - T(0.25) * (ea0 + eb0);
+}
+
 // Cell data d[v][alpha]: v = vertex bits (x = bit 0), alpha = derivative bits.
 // 2D alpha: 0 phi, 1 psi_x, 2 psi_y, 3 phi_xy.
 template <typename T, int MIX>
@@ -166,7 +215,19 @@ __device__ __forceinline__ void gather2d(const Geom &g, Rsrc rphi, Rsrc rgx, Rsr
     d[2][0] = bload(rphi, r1 + i0, T()); d[3][0] = bload(rphi, r1 + i1, T());
     d[0][1] = bload(rgx, r0 + i0, T()); d[1][1] = bload(rgx, r0 + i1, T());
     d[2][1] = bload(rgx, r1 + i0, T()); d[3][1] = bload(rgx, r1 + i1, T());
-    if constexpr (MIX == GALS_MIXED_CENTRAL) {
+    if constexpr (MIX == GALS_MIXED_CELL) {
+        d[0][2] = bload(rgy, r0 + i0, T()); d[1][2] = bload(rgy, r0 + i1, T());
+        d[2][2] = bload(rgy, r1 + i0, T()); d[3][2] = bload(rgy, r1 + i1, T());
+        T ga[4], gb[4], out[4];
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            ga[v] = d[v][1];
+            gb[v] = d[v][2];
+        }
+        cell_cross(ga, gb, T(g.inv_h[0]), T(g.inv_h[1]), out);
+#pragma unroll
+        for (int v = 0; v < 4; v++) d[v][3] = out[v];
+    } else if constexpr (MIX == GALS_MIXED_CENTRAL) {
         const unsigned im = unsigned(cx > 0 ? cx - 1 : 0);
         const unsigned i2 = unsigned(cx + 2 <= g.nc[0] ? cx + 2 : g.nc[0]);
         const T u0[4] = {bload(rgy, r0 + im, T()), bload(rgy, r0 + i0, T()),
@@ -193,6 +254,51 @@ template <typename T, int MIX>
 __device__ __forceinline__ void gather3d(const Geom &g, Rsrc rphi, Rsrc rgx, Rsrc rgy, Rsrc rgz,
                                          int c0, int c1, int c2, T d[8][8])
 {
+    if constexpr (MIX == GALS_MIXED_CELL) {
+        // the 8 vertices' phi and gradients; cross derivatives per facet
+        const unsigned P = unsigned(g.pitch), S = unsigned(g.pitch) * unsigned(g.n[1]);
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+            const unsigned o = unsigned(c2 + (v >> 2)) * S + unsigned(c1 + ((v >> 1) & 1)) * P +
+                               unsigned(c0 + (v & 1));
+            d[v][0] = bload(rphi, o, T());
+            d[v][1] = bload(rgx, o, T());
+            d[v][2] = bload(rgy, o, T());
+            d[v][4] = bload(rgz, o, T());
+        }
+        const T ih[3] = {T(g.inv_h[0]), T(g.inv_h[1]), T(g.inv_h[2])};
+        // (a, b) = (x, y), (x, z), (y, z) into alpha 3, 5, 6; facet level along
+        // the third axis c
+        constexpr int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2}, pc[3] = {2, 1, 0};
+        constexpr int slot[3] = {3, 5, 6};
+#pragma unroll
+        for (int q = 0; q < 3; q++)
+#pragma unroll
+            for (int lc = 0; lc < 2; lc++) {
+                T ga[4], gb[4], out[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int v = ((k & 1) << pa[q]) | (((k >> 1) & 1) << pb[q]) | (lc << pc[q]);
+                    ga[k] = d[v][1 << pa[q]];
+                    gb[k] = d[v][1 << pb[q]];
+                }
+                cell_cross(ga, gb, ih[pa[q]], ih[pb[q]], out);
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int v = ((k & 1) << pa[q]) | (((k >> 1) & 1) << pb[q]) | (lc << pc[q]);
+                    d[v][slot[q]] = out[k];
+                }
+            }
+        // phi_xyz, first order, from psi_z on the xy facet of each z level
+#pragma unroll
+        for (int lz = 0; lz < 2; lz++) {
+            const int b = 4 * lz;
+            const T xyz = (d[b + 3][4] - d[b + 2][4] - d[b + 1][4] + d[b][4]) * (ih[0] * ih[1]);
+#pragma unroll
+            for (int k = 0; k < 4; k++) d[b + k][7] = xyz;
+        }
+        return;
+    }
     const unsigned P = unsigned(g.pitch), S = unsigned(g.pitch) * unsigned(g.n[1]);
     const unsigned xs[4] = {unsigned(c0 > 0 ? c0 - 1 : 0), unsigned(c0), unsigned(c0 + 1),
                             unsigned(c0 + 2 <= g.nc[0] ? c0 + 2 : g.nc[0])};

@@ -80,17 +80,15 @@ hipError_t launch_eval(const gals_ctx *ctx, const void *phi, const void *grad, c
                        int64_t npts, void *val, void *normal, void *curv, hipStream_t s)
 {
     if (npts == 0) return hipSuccess;
+#define GALS_EVAL(T, M) eval_typed<T, M>(ctx, phi, grad, pts, npts, val, normal, curv, s)
     if (ctx->prec == GALS_F32)
-        return ctx->mixed == GALS_MIXED_ZERO
-                   ? eval_typed<float, GALS_MIXED_ZERO>(ctx, phi, grad, pts, npts, val, normal,
-                                                        curv, s)
-                   : eval_typed<float, GALS_MIXED_CENTRAL>(ctx, phi, grad, pts, npts, val,
-                                                           normal, curv, s);
-    return ctx->mixed == GALS_MIXED_ZERO
-               ? eval_typed<double, GALS_MIXED_ZERO>(ctx, phi, grad, pts, npts, val, normal, curv,
-                                                     s)
-               : eval_typed<double, GALS_MIXED_CENTRAL>(ctx, phi, grad, pts, npts, val, normal,
-                                                        curv, s);
+        return ctx->mixed == GALS_MIXED_ZERO   ? GALS_EVAL(float, GALS_MIXED_ZERO)
+               : ctx->mixed == GALS_MIXED_CELL ? GALS_EVAL(float, GALS_MIXED_CELL)
+                                               : GALS_EVAL(float, GALS_MIXED_CENTRAL);
+    return ctx->mixed == GALS_MIXED_ZERO   ? GALS_EVAL(double, GALS_MIXED_ZERO)
+           : ctx->mixed == GALS_MIXED_CELL ? GALS_EVAL(double, GALS_MIXED_CELL)
+                                           : GALS_EVAL(double, GALS_MIXED_CENTRAL);
+#undef GALS_EVAL
 }
 
 __device__ __forceinline__ int64_t node_offset(const Geom &g, int64_t id)

@@ -1,16 +1,19 @@
 // GA-CIR step kernels for gfx950: one thread per grid node, wave64, fused
-// trace + split + gather + Hermite + superconsistent gradient update.
+// trace + split + gather + Hermite + gradient update (superconsistent, or
+// Heun's method along the characteristic).
 //
 // Each node reads only the old state (never updated in place) and writes its
 // new phi, psi with coalesced SoA stores. Departure cells are gathered through
 // the cache hierarchy, so any CFL number is handled by the same code path.
+#include <type_traits>
+
 #include "stream2d.h"
 
 namespace gals {
 
 // Node index -> (i, j[, k]) with 32-bit arithmetic (the host caps the node
 // count below 2^31).
-template <typename T, int KIND, int MIX>
+template <typename T, int KIND, int MIX, int PSI>
 __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st, double dt,
                                                    const T *__restrict__ phi,
                                                    const T *__restrict__ grad,
@@ -25,8 +28,8 @@ __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st
 
     const double x[2] = {g.lo[0] + double(i) * g.h[0], g.lo[1] + double(j) * g.h[1]};
     double X[2];
-    T J[4];
-    trace<T, 2, KIND>(p, st, dt, x, X, J);
+    T J[4];  // superconsistent Jacobian, or (Heun) grad v at the node
+    trace<T, 2, KIND, PSI == GALS_PSI_SUPERCONSISTENT>(p, st, dt, x, X, J);
     const unsigned out = project_foot<2>(g, X);
 
     int cell[2];
@@ -46,11 +49,20 @@ __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st
 
     const int64_t o = int64_t(j) * g.pitch + i;
     phi_o[o] = H;
-    grad_o[o] = J[0] * Hx + J[2] * Hy;
-    grad_o[g.plane + o] = J[1] * Hx + J[3] * Hy;
+    if constexpr (PSI == GALS_PSI_HEUN) {
+        T vf[2], Af[4], ps[2];
+        const T gH[2] = {Hx, Hy};
+        velocity<T, 2, KIND>(p, X, st.c2, vf, Af);
+        heun_gradient<T, 2>(Af, J, T(dt), gH, ps);
+        grad_o[o] = ps[0];
+        grad_o[g.plane + o] = ps[1];
+    } else {
+        grad_o[o] = J[0] * Hx + J[2] * Hy;
+        grad_o[g.plane + o] = J[1] * Hx + J[3] * Hy;
+    }
 }
 
-template <typename T, int KIND, int MIX>
+template <typename T, int KIND, int MIX, int PSI>
 __global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st, double dt,
                                                    const T *__restrict__ phi,
                                                    const T *__restrict__ grad,
@@ -69,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st
                          g.lo[2] + double(k) * g.h[2]};
     double X[3];
     T J[9];
-    trace<T, 3, KIND>(p, st, dt, x, X, J);
+    trace<T, 3, KIND, PSI == GALS_PSI_SUPERCONSISTENT>(p, st, dt, x, X, J);
     const unsigned out = project_foot<3>(g, X);
 
     int cell[3];
@@ -91,9 +103,19 @@ __global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st
 
     const int64_t o = (int64_t(k) * g.n[1] + j) * g.pitch + i;
     phi_o[o] = H;
-    grad_o[o] = J[0] * Hx + J[3] * Hy + J[6] * Hz;
-    grad_o[g.plane + o] = J[1] * Hx + J[4] * Hy + J[7] * Hz;
-    grad_o[2 * g.plane + o] = J[2] * Hx + J[5] * Hy + J[8] * Hz;
+    if constexpr (PSI == GALS_PSI_HEUN) {
+        T vf[3], Af[9], ps[3];
+        const T gH[3] = {Hx, Hy, Hz};
+        velocity<T, 3, KIND>(p, X, st.c2, vf, Af);
+        heun_gradient<T, 3>(Af, J, T(dt), gH, ps);
+        grad_o[o] = ps[0];
+        grad_o[g.plane + o] = ps[1];
+        grad_o[2 * g.plane + o] = ps[2];
+    } else {
+        grad_o[o] = J[0] * Hx + J[3] * Hy + J[6] * Hz;
+        grad_o[g.plane + o] = J[1] * Hx + J[4] * Hy + J[7] * Hz;
+        grad_o[2 * g.plane + o] = J[2] * Hx + J[5] * Hy + J[8] * Hz;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -110,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_tables(Geom g, Vel<double> p,
 // GA-CIR step for the sine stream-function field. Launch: blocks of 64 x 4
 // threads over 64 x 4 node tiles; each wave owns 64 consecutive nodes of one
 // row, so the row table is read once per wave through scalar loads.
-template <typename T, int MIX, bool TAYLOR>
+template <typename T, int MIX, bool TAYLOR, int PSI>
 __global__ __launch_bounds__(kBlock) void k_step2d_stream(
     Geom g, Vel<T> p, Stage<T> st, double dt, const T *__restrict__ coltab,
     const T *__restrict__ rowtab, const T *__restrict__ phi, const T *__restrict__ grad,
@@ -123,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_step2d_stream(
     const int i = int(tx) * 64 + int(threadIdx.x);
     const int j = __builtin_amdgcn_readfirstlane(int(ty) * 4 + int(threadIdx.y));
     if (j >= g.n[1] || i >= g.n[0]) return;
-    stream_node<T, MIX, TAYLOR>(g, p, st, dt, coltab + int64_t(i) * kJet,
+    stream_node<T, MIX, TAYLOR, PSI>(g, p, st, dt, coltab + int64_t(i) * kJet,
                                 rowtab + int64_t(j) * kJet, plane_rsrc(phi, g.plane),
                                 plane_rsrc(grad, g.plane), plane_rsrc(grad + g.plane, g.plane),
                                 phi_o, grad_o, grad_o + g.plane, i, j);
@@ -141,7 +163,7 @@ hipError_t launch_stream_tables(const gals_ctx *ctx, void *coltab, void *rowtab,
     return hipGetLastError();
 }
 
-template <typename T, int MIX>
+template <typename T, int MIX, int PSI>
 static hipError_t launch_stream(const gals_ctx *ctx, const Vel<T> &p, const void *phi,
                                 const void *grad, void *phi_o, void *grad_o, double dt,
                                 double c1, double c2, double c3, const void *coltab,
@@ -150,13 +172,13 @@ static hipError_t launch_stream(const gals_ctx *ctx, const Vel<T> &p, const void
     const Stage<T> st{T(c1), T(c2), T(c3)};
     const unsigned tiles = unsigned((ctx->g.n[0] + 63) / 64) * unsigned((ctx->g.n[1] + 3) / 4);
     const dim3 grid((tiles + 7u) / 8u * 8u);
-    hipLaunchKernelGGL((k_step2d_stream<T, MIX, sizeof(T) == 4>), grid, dim3(64, 4), 0, s,
+    hipLaunchKernelGGL((k_step2d_stream<T, MIX, sizeof(T) == 4, PSI>), grid, dim3(64, 4), 0, s,
                        ctx->g, p, st, dt, (const T *)coltab, (const T *)rowtab, (const T *)phi,
                        (const T *)grad, (T *)phi_o, (T *)grad_o);
     return hipGetLastError();
 }
 
-template <typename T, int KIND, int MIX>
+template <typename T, int KIND, int MIX, int PSI>
 static hipError_t launch_typed(const gals_ctx *ctx, const Vel<T> &p, const void *phi,
                                const void *grad, void *phi_o, void *grad_o, double dt, double c1,
                                double c2, double c3, hipStream_t s)
@@ -166,16 +188,16 @@ static hipError_t launch_typed(const gals_ctx *ctx, const Vel<T> &p, const void 
     if (ctx->dim == 2) {
         if constexpr (KIND == GALS_VEL_AFFINE || KIND == GALS_VEL_STREAM_SIN ||
                       KIND == GALS_VEL_VORTEX || KIND == GALS_VEL_PSEUDO1D) {
-            hipLaunchKernelGGL((k_step2d<T, KIND, MIX>), dim3(blocks), dim3(kBlock), 0, s, ctx->g,
-                               p, st, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
+            hipLaunchKernelGGL((k_step2d<T, KIND, MIX, PSI>), dim3(blocks), dim3(kBlock), 0, s,
+                               ctx->g, p, st, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
                                (T *)grad_o);
             return hipGetLastError();
         }
     } else {
         if constexpr (KIND == GALS_VEL_AFFINE || KIND == GALS_VEL_VECPOT_SIN ||
                       KIND == GALS_VEL_LEVEQUE3D) {
-            hipLaunchKernelGGL((k_step3d<T, KIND, MIX>), dim3(blocks), dim3(kBlock), 0, s, ctx->g,
-                               p, st, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
+            hipLaunchKernelGGL((k_step3d<T, KIND, MIX, PSI>), dim3(blocks), dim3(kBlock), 0, s,
+                               ctx->g, p, st, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
                                (T *)grad_o);
             return hipGetLastError();
         }
@@ -183,68 +205,60 @@ static hipError_t launch_typed(const gals_ctx *ctx, const Vel<T> &p, const void 
     return hipErrorInvalidValue;
 }
 
-template <typename T, int MIX>
+template <typename T, int MIX, int PSI>
 static hipError_t launch_kind(const gals_ctx *ctx, const Vel<T> &p, const void *phi,
                               const void *grad, void *phi_o, void *grad_o, double dt, double c1,
                               double c2, double c3, hipStream_t s)
 {
+#define GALS_KIND_CASE(K)                                                                         \
+    case K:                                                                                       \
+        return launch_typed<T, K, MIX, PSI>(ctx, p, phi, grad, phi_o, grad_o, dt, c1, c2, c3, s);
     switch (ctx->vel_kind) {
-    case GALS_VEL_AFFINE:
-        return launch_typed<T, GALS_VEL_AFFINE, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt, c1,
-                                                     c2, c3, s);
-    case GALS_VEL_STREAM_SIN:
-        return launch_typed<T, GALS_VEL_STREAM_SIN, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt,
-                                                         c1, c2, c3, s);
-    case GALS_VEL_VECPOT_SIN:
-        return launch_typed<T, GALS_VEL_VECPOT_SIN, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt,
-                                                         c1, c2, c3, s);
-    case GALS_VEL_VORTEX:
-        return launch_typed<T, GALS_VEL_VORTEX, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt, c1,
-                                                     c2, c3, s);
-    case GALS_VEL_PSEUDO1D:
-        return launch_typed<T, GALS_VEL_PSEUDO1D, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt, c1,
-                                                       c2, c3, s);
-    case GALS_VEL_LEVEQUE3D:
-        return launch_typed<T, GALS_VEL_LEVEQUE3D, MIX>(ctx, p, phi, grad, phi_o, grad_o, dt,
-                                                        c1, c2, c3, s);
+        GALS_KIND_CASE(GALS_VEL_AFFINE)
+        GALS_KIND_CASE(GALS_VEL_STREAM_SIN)
+        GALS_KIND_CASE(GALS_VEL_VECPOT_SIN)
+        GALS_KIND_CASE(GALS_VEL_VORTEX)
+        GALS_KIND_CASE(GALS_VEL_PSEUDO1D)
+        GALS_KIND_CASE(GALS_VEL_LEVEQUE3D)
     default:
         return hipErrorInvalidValue;
     }
+#undef GALS_KIND_CASE
+}
+
+// Run f with the cross-derivative mode and the gradient update as
+// compile-time constants.
+template <class F>
+static hipError_t with_modes(int mixed, int psi, F &&f)
+{
+    auto on_psi = [&](auto mix) -> hipError_t {
+        if (psi == GALS_PSI_HEUN) return f(mix, std::integral_constant<int, GALS_PSI_HEUN>{});
+        return f(mix, std::integral_constant<int, GALS_PSI_SUPERCONSISTENT>{});
+    };
+    if (mixed == GALS_MIXED_ZERO) return on_psi(std::integral_constant<int, GALS_MIXED_ZERO>{});
+    if (mixed == GALS_MIXED_CELL) return on_psi(std::integral_constant<int, GALS_MIXED_CELL>{});
+    return on_psi(std::integral_constant<int, GALS_MIXED_CENTRAL>{});
 }
 
 hipError_t launch_step(const gals_ctx *ctx, const void *phi, const void *grad, void *phi_o,
                        void *grad_o, double dt, double c1, double c2, double c3,
                        const void *coltab, const void *rowtab, hipStream_t s)
 {
-    if (ctx->vel_kind == GALS_VEL_STREAM_SIN && coltab && rowtab) {
-        if (ctx->prec == GALS_F32)
-            return ctx->mixed == GALS_MIXED_ZERO
-                       ? launch_stream<float, GALS_MIXED_ZERO>(ctx, ctx->vf, phi, grad, phi_o,
-                                                               grad_o, dt, c1, c2, c3, coltab,
-                                                               rowtab, s)
-                       : launch_stream<float, GALS_MIXED_CENTRAL>(ctx, ctx->vf, phi, grad, phi_o,
-                                                                  grad_o, dt, c1, c2, c3, coltab,
-                                                                  rowtab, s);
-        return ctx->mixed == GALS_MIXED_ZERO
-                   ? launch_stream<double, GALS_MIXED_ZERO>(ctx, ctx->vd, phi, grad, phi_o,
-                                                            grad_o, dt, c1, c2, c3, coltab,
-                                                            rowtab, s)
-                   : launch_stream<double, GALS_MIXED_CENTRAL>(ctx, ctx->vd, phi, grad, phi_o,
-                                                               grad_o, dt, c1, c2, c3, coltab,
-                                                               rowtab, s);
-    }
-    if (ctx->prec == GALS_F32) {
-        if (ctx->mixed == GALS_MIXED_ZERO)
-            return launch_kind<float, GALS_MIXED_ZERO>(ctx, ctx->vf, phi, grad, phi_o, grad_o, dt,
-                                                       c1, c2, c3, s);
-        return launch_kind<float, GALS_MIXED_CENTRAL>(ctx, ctx->vf, phi, grad, phi_o, grad_o, dt,
-                                                      c1, c2, c3, s);
-    }
-    if (ctx->mixed == GALS_MIXED_ZERO)
-        return launch_kind<double, GALS_MIXED_ZERO>(ctx, ctx->vd, phi, grad, phi_o, grad_o, dt,
-                                                    c1, c2, c3, s);
-    return launch_kind<double, GALS_MIXED_CENTRAL>(ctx, ctx->vd, phi, grad, phi_o, grad_o, dt, c1,
+    const bool stream = ctx->vel_kind == GALS_VEL_STREAM_SIN && coltab && rowtab;
+    return with_modes(ctx->mixed, ctx->psi, [&](auto mix, auto psi) -> hipError_t {
+        constexpr int MIX = decltype(mix)::value, PSI = decltype(psi)::value;
+        if (stream)
+            return ctx->prec == GALS_F32
+                       ? launch_stream<float, MIX, PSI>(ctx, ctx->vf, phi, grad, phi_o, grad_o,
+                                                        dt, c1, c2, c3, coltab, rowtab, s)
+                       : launch_stream<double, MIX, PSI>(ctx, ctx->vd, phi, grad, phi_o, grad_o,
+                                                         dt, c1, c2, c3, coltab, rowtab, s);
+        return ctx->prec == GALS_F32
+                   ? launch_kind<float, MIX, PSI>(ctx, ctx->vf, phi, grad, phi_o, grad_o, dt, c1,
+                                                  c2, c3, s)
+                   : launch_kind<double, MIX, PSI>(ctx, ctx->vd, phi, grad, phi_o, grad_o, dt, c1,
                                                    c2, c3, s);
+    });
 }
 
 }  // namespace gals

@@ -134,20 +134,23 @@ __device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J, 
 // the boundary treatment, split into a cell and a local coordinate.
 template <typename T>
 struct StreamFoot {
+    StreamJet<T> jet;
     T v0[2], v1[2], v2[2], A0[4], A1[4], A2[4], J[4];
     T d1[2], d2[2];  // stage-2 and stage-3 points minus the node
     unsigned out;    // bit a: the foot left the domain along axis a (Neumann)
     int cell[2];
     double xi[2];
+    double s[2];     // the foot in cell units, after the boundary treatment
 };
 
-template <typename T, bool TAYLOR, class P>
+// CHAIN = false (Heun's gradient update) skips the Jacobian chain (J unset).
+template <typename T, bool TAYLOR, bool CHAIN = true, class P>
 __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const Stage<T> &st,
                                              double dt, const T *__restrict__ U,
                                              const T *__restrict__ Y, int i, int j,
                                              StreamFoot<T> &f)
 {
-    StreamJet<T> jet;
+    StreamJet<T> &jet = f.jet;
     {
         T y[kJet], u[kJet];
 #pragma unroll
@@ -169,7 +172,7 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
     f.d2[0] = -dtT * (T(0.25) * f.v0[0] + T(0.25) * f.v1[0]);
     f.d2[1] = -dtT * (T(0.25) * f.v0[1] + T(0.25) * f.v1[1]);
     stream_stage<T, TAYLOR>(p, jet, x0, y0, f.d2[0], f.d2[1], st.c3, f.v2, f.A2);
-    jacobian_chain<T, 2>(f.A0, f.A1, f.A2, dtT, f.J);
+    if constexpr (CHAIN) jacobian_chain<T, 2>(f.A0, f.A1, f.A2, dtT, f.J);
 
     // foot in cell units, FP64: s = node - dt (v0/6 + v1/6 + 2 v2/3) / h
     double s[2];
@@ -188,12 +191,14 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
         const double fl = fmin(fmax(floor(s[a]), 0.0), double(g.nc[a] - 1));
         f.cell[a] = int(fl);
         f.xi[a] = s[a] - fl;
+        f.s[a] = s[a];
     }
 }
 
 // One GA-CIR step at node (i, j) of a grid with a sine stream-function field:
-// the trace, the gather and the bicubic update.
-template <typename T, int MIX, bool TAYLOR, class P>
+// the trace, the gather and the bicubic update (superconsistent, or Heun's
+// method with grad v at the foot from the node's jet).
+template <typename T, int MIX, bool TAYLOR, int PSI = GALS_PSI_SUPERCONSISTENT, class P>
 __device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Stage<T> &st,
                                             double dt, const T *__restrict__ U,
                                             const T *__restrict__ Y, Rsrc rphi, Rsrc rgx,
@@ -202,7 +207,7 @@ __device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Sta
                                             int j)
 {
     StreamFoot<T> f;
-    stream_trace<T, TAYLOR>(g, p, st, dt, U, Y, i, j, f);
+    stream_trace<T, TAYLOR, PSI == GALS_PSI_SUPERCONSISTENT>(g, p, st, dt, U, Y, i, j, f);
     T d[4][4];
     gather2d<T, MIX>(g, rphi, rgx, rgy, f.cell[0], f.cell[1], d);
     Basis<T> bx, by;
@@ -215,8 +220,19 @@ __device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Sta
 
     const int64_t o = int64_t(j) * g.pitch + i;
     phi_o[o] = H;
-    gx_o[o] = f.J[0] * Hx + f.J[2] * Hy;
-    gy_o[o] = f.J[1] * Hx + f.J[3] * Hy;
+    if constexpr (PSI == GALS_PSI_HEUN) {
+        const double x0 = g.lo[0] + double(i) * g.h[0], y0 = g.lo[1] + double(j) * g.h[1];
+        T vf[2], Af[4], ps[2];
+        const T gH[2] = {Hx, Hy};
+        stream_stage<T, TAYLOR>(p, f.jet, x0, y0, T((f.s[0] - double(i)) * g.h[0]),
+                                T((f.s[1] - double(j)) * g.h[1]), st.c2, vf, Af);
+        heun_gradient<T, 2>(Af, f.A0, T(dt), gH, ps);
+        gx_o[o] = ps[0];
+        gy_o[o] = ps[1];
+    } else {
+        gx_o[o] = f.J[0] * Hx + f.J[2] * Hy;
+        gy_o[o] = f.J[1] * Hx + f.J[3] * Hy;
+    }
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin by id, and each XCD has its

@@ -9,10 +9,12 @@ TOL64 = 1e-12     # FP64 parity bar: normwise relative error per field
 
 
 def gpu_advance(dim, ncell, lo, hi, kind, params, period, phi0, psi0, t0, dt, steps,
-                dtype="float64", mixed=pkg.MIXED_CENTRAL, stream=None, bc=pkg.BC_NEUMANN):
+                dtype="float64", mixed=pkg.MIXED_CENTRAL, stream=None, bc=pkg.BC_NEUMANN,
+                psi=pkg.PSI_SUPERCONSISTENT):
     import torch
     g = pkg.Grid(ncell, lo, hi, dtype=dtype, mixed=mixed, bc=bc, device=0)
     g.set_velocity(kind, params, period)
+    g.set_psi_update(psi)
     st = g.from_numpy(phi0, psi0)
     g.advance(st, t0, dt, steps, stream=stream)
     torch.cuda.synchronize()
@@ -20,9 +22,9 @@ def gpu_advance(dim, ncell, lo, hi, kind, params, period, phi0, psi0, t0, dt, st
 
 
 def oracle_advance(dim, ncell, lo, hi, kind, params, period, phi0, psi0, t0, dt, steps,
-                   mixed=pkg.MIXED_CENTRAL, bc=pkg.BC_NEUMANN):
+                   mixed=pkg.MIXED_CENTRAL, bc=pkg.BC_NEUMANN, psi=pkg.PSI_SUPERCONSISTENT):
     return oracle.advance(dim, ncell, lo, hi, kind, params, period, phi0, psi0, t0, dt, steps,
-                          mixed_mode=mixed, bc=bc)
+                          mixed_mode=mixed, bc=bc, psi_update=psi)
 
 
 def rel(a, b):

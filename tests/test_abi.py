@@ -46,6 +46,7 @@ def test_create_validation():
     assert _ctx(ncell=(1, 7, 5))[0] == pkg.EINVAL
     assert _ctx(prec=3)[0] == pkg.EINVAL
     assert _ctx(mixed=7)[0] == pkg.EINVAL
+    assert _ctx(mixed=pkg.MIXED_CELL)[0] == pkg.OK
     assert _ctx(bc=2)[0] == pkg.EINVAL
     assert _ctx(bc=pkg.BC_EXTRAPOLATE)[0] == pkg.OK
     assert _ctx(device=-2)[0] in (pkg.EINVAL, pkg.EHIP)
@@ -182,7 +183,8 @@ def test_batch_create_validation():
     assert _batch([(8, 8), (1, 8)])[0] == pkg.EINVAL
     assert b"problem 1 axis 0" in L.gals_last_error()
     assert _batch([(8, 8)], prec=5)[0] == pkg.EINVAL
-    assert _batch([(8, 8)], mixed=1)[0] == pkg.EINVAL
+    assert _batch([(8, 8)], mixed=3)[0] == pkg.EINVAL
+    assert _batch([(8, 8)], mixed=pkg.MIXED_CELL)[0] == pkg.OK
     assert _batch([(8, 8)], bc=3)[0] == pkg.EINVAL
     assert _batch([(8, 8)], device=-3)[0] == pkg.EINVAL
     assert _batch([(8, 8)], lo=[0.0, 1.0], hi=[1.0, 1.0])[0] == pkg.EINVAL
@@ -338,3 +340,22 @@ def test_adjoint_entry_points_validate_on_a_host_only_context():
     assert L.gals_adjoint_step(ctx3, st, st, 0.0, 0.01, lam, ctypes.c_void_p(1 << 35), dS, ws,
                                1 << 30, None) == pkg.ENOTSUP
     L.gals_destroy(ctx3)
+
+
+def test_psi_update_option():
+    L = pkg.lib()
+    rc, ctx = _ctx()
+    assert L.gals_set_psi_update(ctx, pkg.PSI_HEUN) == pkg.OK
+    assert L.gals_set_psi_update(ctx, 2) == pkg.EINVAL
+    assert L.gals_set_psi_update(None, 0) == pkg.EINVAL
+    # the adjoint differentiates the superconsistent update only
+    P = ctypes.POINTER(ctypes.c_double)
+    rc2, c2 = _ctx(dim=2, ncell=(8, 8, 1), prec=pkg.F64)
+    good = np.array([0.01, 1, 2], dtype=np.float64)
+    assert L.gals_set_velocity(c2, pkg.STREAM_SIN, good.ctypes.data_as(P), 3, 0.0) == pkg.OK
+    assert L.gals_set_psi_update(c2, pkg.PSI_HEUN) == pkg.OK
+    v = ctypes.c_void_p
+    assert L.gals_adjoint_step(c2, v(1 << 30), v(1 << 31), 0.0, 0.01, v(1 << 32), v(1 << 33),
+                               v(1 << 34), v(1 << 35), 1 << 30, None) == pkg.ENOTSUP
+    L.gals_destroy(ctx)
+    L.gals_destroy(c2)
