@@ -21,6 +21,15 @@ stream-function amplitudes on 1024^2 cells: a 200-step FP32 advance that
 keeps a checkpoint every 20 steps, the loss and its seed, and the reverse
 sweep (each segment recomputed from its checkpoint, then 20 adjoint steps).
 
+--workload variants times the 2048^2 advance (FP32) for each cross-derivative
+reconstruction (central (A), cell-based (B), zero) with the superconsistent
+and with Heun's gradient update.
+
+--workload volume runs the 3D deformation test of the paper's volume-loss
+tables (LeVeque's field x cos(pi t / 2.5), dt = h, to t = 2.5; a sphere and a
+cube at n = 50, 100, 150, 200, FP64) and reports the relative volume change
+beside the paper's GA-CIR rows, and the 200^3 advance's throughput.
+
 --workload batched times the many-problem case instead: 512 independent
 grids of round(2^U(5,9)) cells per side, each with its own circles and
 stream function, 256 steps of dt = 2/256 per benchmark step, advanced
@@ -48,6 +57,9 @@ VALU_F32_PEAK_TFLOPS = 78.6
 # bicubic value and gradient 80, gradient update 6.
 ALG_FLOPS_PER_NODE = 515
 BYTES_PER_NODE = 24  # FP32 state: 3 planes read once + 3 planes written once
+# The cell-based (B) cross derivatives replace the 8 flops of the central
+# differences by 4 edge differences and 4 weighted vertex sums (28 flops).
+VARIANT_B_FLOPS_PER_NODE = ALG_FLOPS_PER_NODE - 8 + 28
 
 
 def log(msg):
@@ -106,7 +118,8 @@ def main():
     ap.add_argument("--inner", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched", "adjoint"], default="single")
+    ap.add_argument("--workload", choices=["single", "batched", "adjoint", "variants", "volume"],
+                    default="single")
     ap.add_argument("--tiles", default="",
                     help="batched only: wave widths per size class, e.g. 64,0,16,64, "
                          "instead of the autotuner's choice")
@@ -130,6 +143,10 @@ def main():
         return bench_batched(args)
     if args.workload == "adjoint":
         return bench_adjoint(args)
+    if args.workload == "variants":
+        return bench_variants(args)
+    if args.workload == "volume":
+        return bench_volume(args)
     dev = torch.device("cuda", 0)
     w = inputs.stream_circles()
     inner = args.inner or w["steps"]
@@ -473,6 +490,126 @@ def bench_adjoint(args):
         "adjoint_step_us": adj_us,
         "node_steps_per_s": nodes * (2 * steps + recompute) / (ms * 1e-3),
         "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_variants(args):
+    import numpy as np
+    import torch
+
+    import paper_0905_3409_amd as pkg
+    from paper_0905_3409_amd import inputs
+
+    w = inputs.stream_circles()
+    inner = args.inner or w["steps"]
+    n = w["ncell"][0]
+    nodes = (n + 1) ** 2
+    s = torch.cuda.current_stream()
+    names = {pkg.MIXED_CENTRAL: "central (A)", pkg.MIXED_CELL: "cell-based (B)",
+             pkg.MIXED_ZERO: "zero"}
+    table = {}
+    for mixed in (pkg.MIXED_CENTRAL, pkg.MIXED_CELL, pkg.MIXED_ZERO):
+        g = pkg.Grid(w["ncell"], w["lo"], w["hi"], dtype="float32", mixed=mixed)
+        g.set_velocity(w["kind"], w["params"], w["period"])
+        ref = g.from_numpy(w["phi0"], w["psi0"])
+        st = ref.clone()
+        for psi, pname in ((pkg.PSI_SUPERCONSISTENT, "superconsistent"), (pkg.PSI_HEUN, "heun")):
+            g.set_psi_update(psi)
+            times = []
+            for k in range(args.warmup + args.steps):
+                st.copy_(ref)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(s)
+                g.advance(st, 0.0, w["dt"], inner)
+                b.record(s)
+                torch.cuda.synchronize()
+                if k >= args.warmup:
+                    times.append(a.elapsed_time(b))
+            ms = float(np.mean(times))
+            norms = g.norms(st, ref, 1.5 / n, 3.0 / n)
+            us = ms * 1e3 / inner
+            table[f"{names[mixed]}, {pname}"] = {
+                "step_us": us, "node_updates_per_s": nodes / (us * 1e-6),
+                "l1_shape_error": norms[2]}
+            log(f"{names[mixed]:15s} {pname:15s}: {us:6.2f} us/step, "
+                f"{nodes / us / 1e3:.1f} G node-upd/s, L1 shape error {norms[2]:.3e}")
+        del g, ref, st
+    for m in names.values():
+        table[f"{m}, heun / superconsistent time"] = (table[f"{m}, heun"]["step_us"] /
+                                                     table[f"{m}, superconsistent"]["step_us"])
+    main = table["cell-based (B), superconsistent"]
+    flops = nodes * VARIANT_B_FLOPS_PER_NODE / (main["step_us"] * 1e-6) / 1e12
+    line = {
+        "metric": "GALS node-updates/s, cell-based (B) cross derivatives (2048^2, FP32)",
+        "value": main["node_updates_per_s"], "unit": "node-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": main["step_us"] * inner / 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "stream_circles: 2048^2 cells, 4 seeded circles, 8-mode sine "
+                               "stream function x cos(pi t/2), 1024 steps, CFL 0.8",
+                   "time_steps_per_step": inner, "seed": w["seed"]},
+        "roofline": {"bound": "alu", "achieved": flops, "peak": VALU_F32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flops / VALU_F32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_step2d_stream<float, CELL, taylor, superconsistent>",
+                     "flops_per_launch": nodes * VARIANT_B_FLOPS_PER_NODE,
+                     "avg_launch_us": main["step_us"]},
+        "variants": table,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_volume(args):
+    import numpy as np
+    import torch
+
+    import paper_0905_3409_amd as pkg
+    from paper_0905_3409_amd import inputs
+
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "volume_loss.json")))
+    table = {}
+    timing = None
+    for shape in ("sphere", "cube"):
+        for n in golden["n"]:
+            w = inputs.leveque_shape(shape, n)
+            g = pkg.Grid(w["ncell"], w["lo"], w["hi"], dtype="float64")
+            g.set_velocity(w["kind"], w["params"], w["period"])
+            ref = g.from_numpy(w["phi0"], w["psi0"])
+            st = ref.clone()
+            s = torch.cuda.current_stream()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            g.advance(st, 0.0, w["dt"], w["steps"])
+            b.record(s)
+            out = g.norms(st, ref, 1.5 / n, 3.0 / n)
+            ms = a.elapsed_time(b)
+            loss = 100.0 * (out[4] - out[5]) / out[5]
+            paper = golden[shape][golden["n"].index(n)]
+            table[f"{shape} n={n}"] = {"volume_change_percent": loss, "paper_percent": paper,
+                                       "steps": w["steps"], "advance_ms": ms}
+            log(f"{shape:6s} n={n:3d}: volume change {loss:+.2f} % (paper {paper:+.1f} %), "
+                f"{w['steps']} steps in {ms:.1f} ms")
+            if n == golden["n"][-1] and shape == "sphere":
+                nodes = (n + 1) ** 3
+                timing = (nodes, w["steps"], ms)
+            del g, ref, st
+            torch.cuda.empty_cache()
+    nodes, steps, ms = timing
+    value = nodes * steps / (ms * 1e-3)
+    line = {
+        "metric": "GALS node-updates/s, 3D deformation test (200^3, FP64), and volume change "
+                  "against the paper's tables",
+        "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "leveque_shape: LeVeque 3D deformation x cos(pi t/2.5), dt = h, "
+                               "t = 0..2.5; sphere r 0.15 and cube 0.3 at (0.35,0.35,0.35)",
+                   "grids": golden["n"], "volume": "prod(h) sum H_eps(-phi), eps = 1.5 h"},
+        "volume_table": table,
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
     return 0

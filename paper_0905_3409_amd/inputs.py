@@ -77,6 +77,28 @@ def sdf_union(coords, centres, radii):
     return best, np.concatenate(grad)
 
 
+def sdf_box(coords, centre, half):
+    """Signed distance to an axis-aligned box (centre, half side lengths),
+    negative inside, with its gradient: outside, the direction from the
+    nearest point of the box; inside, the outward normal of the nearest face
+    (lowest axis on ties; +x side at the exact centre)."""
+    dim = len(coords)
+    s = [np.where(coords[a] - centre[a] >= 0, 1.0, -1.0) for a in range(dim)]
+    q = [np.abs(coords[a] - centre[a]) - half[a] for a in range(dim)]
+    qp = [np.maximum(qa, 0.0) for qa in q]
+    outside = np.sqrt(sum(v * v for v in qp))
+    qmax = np.max(np.stack(q), axis=0)
+    phi = outside + np.minimum(qmax, 0.0)
+    kmax = np.argmax(np.stack(q), axis=0)
+    safe = np.where(outside > 0, outside, 1.0)
+    grad = []
+    for a in range(dim):
+        g_out = qp[a] / safe * s[a]
+        g_in = np.where(kmax == a, s[a], 0.0)
+        grad.append(np.where(outside > 0, g_out, g_in))
+    return phi, np.concatenate(grad)
+
+
 def gaussian_bump(coords, x0, r0=0.15):
     """exp(-|x - x0|^2) - exp(-r0^2) and its gradient (the smooth initial data
     of the paper's accuracy tests)."""
@@ -257,6 +279,25 @@ def adjoint_circles(seed=5, n=1024, steps=200, nmodes=16, cfl=0.8, target_seed=6
     return dict(name="adjoint_circles", ncell=ncell, modes=modes, amps=amps, target_amps=target,
                 dt=float(dt), steps=int(steps), period=0.0, t0=0.0, eps=1.5 / n, phi0=phi,
                 psi0=psi, seed=seed, target_seed=target_seed, cfl=cfl)
+
+
+def leveque_shape(shape="sphere", n=50, period=2.5):
+    """The 3D deformation test with volume loss (sec. 6.2): LeVeque's field
+    x cos(pi t / T), T = 2.5, on n^3 cells of [0,1]^3, dt = h, run to t = T
+    (2.5 n steps); a sphere of radius 0.15 or a cube of side 0.3, centred at
+    (0.35, 0.35, 0.35)."""
+    ncell = (n, n, n)
+    coords = node_grid(ncell)
+    c = (0.35, 0.35, 0.35)
+    if shape == "sphere":
+        phi, psi = sdf_union(coords, [c], [0.15])
+    elif shape == "cube":
+        phi, psi = sdf_box(coords, c, (0.15, 0.15, 0.15))
+    else:
+        raise ValueError(shape)
+    steps = int(round(period * n))
+    return _workload(f"leveque_{shape}", ncell, LEVEQUE3D, np.zeros(0), period, 1.0 / n, steps,
+                     phi, psi, shape=shape)
 
 
 def random_points(seed, npts, dim, lo=0.0, hi=1.0):
