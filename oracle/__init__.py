@@ -58,6 +58,7 @@ def _load():
     lib.orc_norms.argtypes = [i, L, D, D, D, D, D, D, d, d, D]
     lib.orc_max_speed.argtypes = [i, L, D, D, i, D, l, d, d]
     lib.orc_max_speed.restype = d
+    lib.orc_apply_inflow.argtypes = [i, L, D, D, i, D, l, d, d, D, D, D, D, D]
     lib.orc_grad_cs.argtypes = [L, D, D, D, l, d, i, i, D, D, d, d, l, D, D, d, D, D]
     lib.orc_num_threads.argtypes = []
     _lib = lib
@@ -222,3 +223,22 @@ def grad_cs(ncell, lo, hi, params, period, phi0, psi0, t0, dt, steps, lam=None,
                                _dp(phi0), _dp(psi0), t0, dt, steps, _dp(lam), _dp(tgt), eps,
                                ctypes.byref(val), _dp(grad)), "grad_cs")
     return val.value, grad.reshape(4, 4)
+
+
+def advance_inflow(dim, ncell, lo, hi, kind, params, period, phi, psi, t0, dt, steps, inflow,
+                   mixed_mode=MIXED_CENTRAL, psi_update=PSI_SUPERCONSISTENT):
+    """Advance with Dirichlet inflow data: inflow(t) returns (phi_b, grad_b,
+    phit_b) at every node for time t; each step is followed by
+    orc_apply_inflow at its end time. Feet outside the domain are projected
+    (homogeneous Neumann) as with bc 0."""
+    nc, lo_, hi_, ncp = _geom(ncell, lo, hi)
+    p, npar = _params(params)
+    for n in range(steps):
+        t = t0 + n * dt
+        phi, psi = advance(dim, ncell, lo, hi, kind, params, period, phi, psi, t, dt, 1,
+                           mixed_mode=mixed_mode, bc=BC_NEUMANN, psi_update=psi_update)
+        pb, gb, tb = (_f64(a) for a in inflow(t + dt))
+        _check(_load().orc_apply_inflow(dim, ncp, _dp(lo_), _dp(hi_), kind, _dp(p), npar, period,
+                                        t + dt, _dp(phi), _dp(psi), _dp(pb), _dp(gb), _dp(tb)),
+               "apply_inflow")
+    return phi, psi

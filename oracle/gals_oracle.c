@@ -666,6 +666,53 @@ int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
     return err;
 }
 
+/* Dirichlet inflow data (sec. 4.1): at a boundary node where the velocity at
+ * time t (the end of the step) points into the domain, phi is prescribed,
+ * the tangential gradient components follow from it, and the normal one
+ * from the equation, phi_n = -(phi_t + sum of tangential v_a phi_a) / v_n.
+ * phi_b, grad_b (dim planes) and phit_b hold the prescribed phi, its
+ * gradient and its time derivative at the nodes; where the flow enters
+ * through more than one face (edges, corners) every gradient component is
+ * taken from grad_b. Other nodes are left as they are. */
+int orc_apply_inflow(int dim, const long *ncell, const double *lo, const double *hi,
+                     int kind, const double *params, long nparams, double period, double t,
+                     double *phi, double *psi, const double *phi_b, const double *grad_b,
+                     const double *phit_b)
+{
+    grid_t g;
+    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || !phi_b || !grad_b || !phit_b)
+        return -1;
+    long N = g.nodes;
+    int bad = 0;
+    for (long idx = 0; idx < N; idx++) {
+        long ijk[MAXD];
+        double x[MAXD], v[MAXD], G[9];
+        int in[MAXD], nin = 0, axis = -1;
+        node_coords(&g, idx, ijk);
+        int on_boundary = 0;
+        for (int a = 0; a < dim; a++)
+            if (ijk[a] == 0 || ijk[a] == g.nc[a]) on_boundary = 1;
+        if (!on_boundary) continue;
+        for (int a = 0; a < dim; a++) x[a] = g.lo[a] + (double)ijk[a] * g.h[a];
+        if (orc_velocity(dim, kind, params, nparams, period, x, t, v, G)) { bad = 1; break; }
+        for (int a = 0; a < dim; a++) {
+            /* low face: outward normal -e_a, inflow if v_a > 0; high face: v_a < 0 */
+            in[a] = (ijk[a] == 0 && v[a] > 0.0) || (ijk[a] == g.nc[a] && v[a] < 0.0);
+            if (in[a]) { nin++; axis = a; }
+        }
+        if (nin == 0) continue;
+        phi[idx] = phi_b[idx];
+        for (int a = 0; a < dim; a++) psi[a * N + idx] = grad_b[a * N + idx];
+        if (nin == 1) {
+            double s = phit_b[idx];
+            for (int a = 0; a < dim; a++)
+                if (a != axis) s += v[a] * grad_b[a * N + idx];
+            psi[axis * N + idx] = -s / v[axis];
+        }
+    }
+    return bad ? -1 : 0;
+}
+
 int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *hi,
                    int kind, const double *params, long nparams, double period,
                    int mixed_mode, int bc, int psi_update, const double *phi,

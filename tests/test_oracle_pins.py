@@ -942,3 +942,79 @@ def test_volume_loss_n50_matches_the_paper(shape):
     print(f"{shape}: volume change {change:.2f} % (paper {paper} %)")
     assert change < 0
     assert abs(change - paper) <= 1.0
+
+
+# ---------------------------------------------------------------------------
+# Sec. 4.1: Dirichlet inflow data, the normal derivative from the equation
+# ---------------------------------------------------------------------------
+def _translation_inflow(p, b, coords):
+    """Exact solution data p(x - b t) of phi_t + b . grad phi = 0."""
+    dim = len(coords)
+
+    def data(t):
+        shifted = [coords[a] - b[a] * t for a in range(dim)]
+        grads = [p.deriv(unit(dim, a))(*shifted) for a in range(dim)]
+        phit = -sum(b[a] * grads[a] for a in range(dim))
+        return p(*shifted), np.concatenate(grads), phit
+    return data
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_inflow_data_make_translation_exact_everywhere(dim):
+    """Constant velocity entering through the low faces, total-degree-3
+    data: with the exact solution prescribed at the inflow boundary (phi,
+    its tangential derivatives and phi_t, the normal derivative from the
+    equation) every node is exact, boundary nodes included; the homogeneous
+    Neumann treatment is not."""
+    rng = np.random.default_rng(150 + dim)
+    n = 12 if dim == 2 else 7
+    ncell = (n,) * dim
+    p = Poly.random_total_degree(rng, dim, 3)
+    coords = inputs.node_grid(ncell)
+    phi, psi = poly_state(p, coords)
+    b = np.array([0.6, 0.35, 0.45][:dim])
+    params = inputs.affine_params(b, np.zeros(dim), np.zeros((dim, dim)))
+    dt, steps = 0.7 / n, 5
+    data = _translation_inflow(p, b, coords)
+    ph, ps = oracle.advance_inflow(dim, ncell, np.zeros(dim), np.ones(dim), inputs.AFFINE, params,
+                                   0.0, phi, psi, 0.0, dt, steps, data)
+    want_phi, want_psi, _ = data(steps * dt)
+    assert rel_err(ph, want_phi) < 1e-12
+    assert rel_err(ps, want_psi) < 1e-11
+    nph, _ = oracle.advance(dim, ncell, np.zeros(dim), np.ones(dim), inputs.AFFINE, params, 0.0,
+                            phi, psi, 0.0, dt, steps)
+    assert rel_err(nph, want_phi) > 1e-4
+
+
+def test_lte_pseudo1d_orders_with_inflow_data():
+    """Pseudo-1D flow (eq. velocity_1) with the exact solution as inflow
+    data on x = 0 and y = 0: the local truncation error keeps its orders
+    (4 in phi, 3 in psi) up to the inflow boundary (nodes with x, y <= 3/4,
+    away from the outflow faces' one-sided stencils)."""
+    r = math.sqrt(2 + PI)
+    e = np.array([math.sqrt(2), math.sqrt(PI)]) / r
+    hs, ephi, epsi = [], [], []
+    for n in (32, 64, 128, 256):
+        ncell = (n, n)
+        h = 1.0 / n
+        dt = h / 2
+        coords = inputs.node_grid(ncell)
+        phi, psi = inputs.gaussian_bump(coords, (0.5, 0.5))
+        s = e[0] * coords[0] + e[1] * coords[1]
+
+        def data(t):
+            ph_, ps_, _ = _pseudo1d_exact(coords, t)
+            g = ps_.reshape(2, -1)
+            return ph_, ps_, -np.exp(s) * (e[0] * g[0] + e[1] * g[1])
+
+        ph, ps = oracle.advance_inflow(2, ncell, [0, 0], [1, 1], inputs.PSEUDO1D, [], 0.0, phi,
+                                       psi, 0.0, dt, 16, data)
+        ex_phi, ex_psi, _ = _pseudo1d_exact(coords, 16 * dt)
+        m = (coords[0] <= 0.75) & (coords[1] <= 0.75)
+        hs.append(h)
+        ephi.append(np.abs(ph - ex_phi)[m].max())
+        epsi.append(np.abs(ps - ex_psi).reshape(2, -1)[:, m].max())
+    op = observed_orders(hs, ephi)
+    og = observed_orders(hs, epsi)
+    assert op[-1] > 3.6 and op[-1] < 4.4, (ephi, op)
+    assert og[-1] > 2.6 and og[-1] < 3.4, (epsi, og)
