@@ -78,8 +78,11 @@ enum { GALS_PSI_SUPERCONSISTENT = 0, GALS_PSI_HEUN = 1 };
  * normal, has zero normal derivative. GALS_BC_EXTRAPOLATE: the nearest
  * boundary cell's polynomial is evaluated outside its cell (exact for
  * polynomial data, but it amplifies values when feet land more than about one
- * cell out, e.g. a rotation at CFL > 1 in the corners). */
-enum { GALS_BC_NEUMANN = 0, GALS_BC_EXTRAPOLATE = 1 };
+ * cell out, e.g. a rotation at CFL > 1 in the corners). GALS_BC_INFLOW:
+ * Dirichlet inflow data (sec. 4.1) from gals_set_inflow_data at boundary
+ * nodes where the flow enters, feet outside the domain projected as with
+ * GALS_BC_NEUMANN. */
+enum { GALS_BC_NEUMANN = 0, GALS_BC_EXTRAPOLATE = 1, GALS_BC_INFLOW = 2 };
 
 /* Velocity fields v(x,t) = c(t) v_s(x), c(t) = cos(pi t / period) when
  * period > 0, else 1. Parameter vectors (FP64):
@@ -143,6 +146,23 @@ int gals_set_velocity(gals_ctx *ctx, int kind, const double *params, int64_t npa
  * GALS_PSI_HEUN. Batches and the adjoint use the superconsistent update. */
 int gals_set_psi_update(gals_ctx *ctx, int mode);
 
+/* Dirichlet inflow data for a GALS_BC_INFLOW context (sec. 4.1): device
+ * arrays in the state layout, phi_b (one plane), grad_b (dim planes) and
+ * phit_b (one plane), read at boundary nodes only. After each step (ending
+ * at time t), at a boundary node where v(x, t) enters the domain through one
+ * face, phi = phi_b, the tangential gradient = grad_b's, and the normal
+ * derivative = -(phit_b + tangential v . grad_b) / v_n, from the equation;
+ * where the flow enters through several faces (edges, corners) every
+ * component comes from grad_b. The data are for the end time of the step
+ * (for time-dependent data advance one step at a time and update them).
+ * The flow enters through face a where its inward normal component exceeds
+ * 1e-6 max(|v|, h_a / dt), so a face that is a streamline (a no-penetration
+ * wall) or a stagnation point takes no data whatever the rounding of v.
+ * The caller keeps the arrays alive while they are set. EINVAL for a
+ * context of another boundary treatment. */
+int gals_set_inflow_data(gals_ctx *ctx, const void *phi_b, const void *grad_b,
+                         const void *phit_b);
+
 /* Advance phi and grad (device, in place) by `steps` GA-CIR steps of size dt
  * from time t0 (sec. 4, steps 1-3, with the superconsistent update of eq.
  * superconsistency). Step n goes from t0 + n*dt to t0 + (n+1)*dt; times are
@@ -150,7 +170,8 @@ int gals_set_psi_update(gals_ctx *ctx, int mode);
  * away (any CFL); feet outside the domain follow the context's boundary
  * treatment. Async. EINVAL on NULL or overlapping state/workspace
  * pointers, workspace smaller than gals_workspace_bytes, non-finite or
- * non-positive dt, non-finite t0, steps < 0, or no velocity set. */
+ * non-positive dt, non-finite t0, steps < 0, no velocity set, or a
+ * GALS_BC_INFLOW context without inflow data. */
 int gals_advance(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int64_t steps,
                  void *workspace, size_t workspace_bytes, void *stream);
 
@@ -196,7 +217,8 @@ int gals_norms(gals_ctx *ctx, const void *phi, const void *grad, const void *phi
  * the state layout (3 planes of plane_stride elements, lam_phi, lam_x,
  * lam_y); dF/dS is 16 FP64 values in device memory, index 4 (m-1) + (n-1).
  * The state adjoint sums with FP64 atomics, so its last bits vary from run to
- * run; dF/dS is reduced in a fixed order. Other fields or 3D grids: ENOTSUP.
+ * run; dF/dS is reduced in a fixed order. Other fields, 3D grids, Heun's
+ * gradient update or GALS_BC_INFLOW contexts: ENOTSUP.
  * ------------------------------------------------------------------------- */
 
 /* Bytes of a checkpoint store for `steps` steps saved every `every` steps:

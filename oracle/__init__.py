@@ -41,8 +41,10 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
-        build()
+    if not os.path.exists(_LIB_PATH) or any(
+            os.path.getmtime(s) > os.path.getmtime(_LIB_PATH)
+            for s in _SRCS + [os.path.join(_HERE, "gals_oracle.h")]):
+        build()  # missing or older than its sources
     lib = ctypes.CDLL(_LIB_PATH)
     D = ctypes.POINTER(ctypes.c_double)
     L = ctypes.POINTER(ctypes.c_long)
@@ -58,7 +60,7 @@ def _load():
     lib.orc_norms.argtypes = [i, L, D, D, D, D, D, D, d, d, D]
     lib.orc_max_speed.argtypes = [i, L, D, D, i, D, l, d, d]
     lib.orc_max_speed.restype = d
-    lib.orc_apply_inflow.argtypes = [i, L, D, D, i, D, l, d, d, D, D, D, D, D]
+    lib.orc_apply_inflow.argtypes = [i, L, D, D, i, D, l, d, d, d, D, D, D, D, D]
     lib.orc_grad_cs.argtypes = [L, D, D, D, l, d, i, i, D, D, d, d, l, D, D, d, D, D]
     lib.orc_num_threads.argtypes = []
     _lib = lib
@@ -239,6 +241,7 @@ def advance_inflow(dim, ncell, lo, hi, kind, params, period, phi, psi, t0, dt, s
                            mixed_mode=mixed_mode, bc=BC_NEUMANN, psi_update=psi_update)
         pb, gb, tb = (_f64(a) for a in inflow(t + dt))
         _check(_load().orc_apply_inflow(dim, ncp, _dp(lo_), _dp(hi_), kind, _dp(p), npar, period,
-                                        t + dt, _dp(phi), _dp(psi), _dp(pb), _dp(gb), _dp(tb)),
+                                        t + dt, dt, _dp(phi), _dp(psi), _dp(pb), _dp(gb),
+                                        _dp(tb)),
                "apply_inflow")
     return phi, psi

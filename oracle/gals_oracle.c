@@ -673,14 +673,20 @@ int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
  * phi_b, grad_b (dim planes) and phit_b hold the prescribed phi, its
  * gradient and its time derivative at the nodes; where the flow enters
  * through more than one face (edges, corners) every gradient component is
- * taken from grad_b. Other nodes are left as they are. */
+ * taken from grad_b. Other nodes are left as they are. The flow enters
+ * through face a when its inward normal component exceeds INFLOW_THETA
+ * max(|v|, h_a / dt), dt the step: along a face that is a streamline
+ * (v_n = 0 analytically) or at a stagnation point the rounding of v must not
+ * decide, and phi_n, which divides by v_n, stays bounded. */
+#define INFLOW_THETA 1e-6
 int orc_apply_inflow(int dim, const long *ncell, const double *lo, const double *hi,
                      int kind, const double *params, long nparams, double period, double t,
-                     double *phi, double *psi, const double *phi_b, const double *grad_b,
-                     const double *phit_b)
+                     double dt, double *phi, double *psi, const double *phi_b,
+                     const double *grad_b, const double *phit_b)
 {
     grid_t g;
-    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || !phi_b || !grad_b || !phit_b)
+    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || !phi_b || !grad_b || !phit_b ||
+        !(dt > 0.0))
         return -1;
     long N = g.nodes;
     int bad = 0;
@@ -695,9 +701,12 @@ int orc_apply_inflow(int dim, const long *ncell, const double *lo, const double 
         if (!on_boundary) continue;
         for (int a = 0; a < dim; a++) x[a] = g.lo[a] + (double)ijk[a] * g.h[a];
         if (orc_velocity(dim, kind, params, nparams, period, x, t, v, G)) { bad = 1; break; }
+        double speed2 = 0.0;
+        for (int a = 0; a < dim; a++) speed2 += v[a] * v[a];
         for (int a = 0; a < dim; a++) {
+            const double vmin = INFLOW_THETA * fmax(sqrt(speed2), g.h[a] / dt);
             /* low face: outward normal -e_a, inflow if v_a > 0; high face: v_a < 0 */
-            in[a] = (ijk[a] == 0 && v[a] > 0.0) || (ijk[a] == g.nc[a] && v[a] < 0.0);
+            in[a] = (ijk[a] == 0 && v[a] > vmin) || (ijk[a] == g.nc[a] && v[a] < -vmin);
             if (in[a]) { nin++; axis = a; }
         }
         if (nin == 0) continue;

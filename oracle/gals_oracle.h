@@ -92,15 +92,16 @@ int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *h
                    const double *psi, double t, double dt, const long *nodes, long count,
                    double *phi_out, double *psi_out);
 
-/* Dirichlet inflow data (sec. 4.1) applied after a step ending at time t:
- * at boundary nodes where v(x, t) enters the domain, phi = phi_b, the
+/* Dirichlet inflow data (sec. 4.1) applied after a step of size dt ending
+ * at time t: at boundary nodes where v(x, t) enters the domain (inward
+ * normal component above 1e-6 max(|v|, h_a / dt)), phi = phi_b, the
  * tangential gradient = grad_b's, and the normal derivative from the
  * equation, -(phit_b + tangential v . grad_b) / v_n (all components from
  * grad_b where the flow enters through several faces). In place. */
 int orc_apply_inflow(int dim, const long *ncell, const double *lo, const double *hi,
                      int kind, const double *params, long nparams, double period, double t,
-                     double *phi, double *psi, const double *phi_b, const double *grad_b,
-                     const double *phit_b);
+                     double dt, double *phi, double *psi, const double *phi_b,
+                     const double *grad_b, const double *phit_b);
 
 /* Value, gradient, Hessian, normal and curvature of the Hermite interpolant at
  * npts points (sec. 3.2, eqs. surface_normal and curvature). Any output may be

@@ -27,7 +27,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOTSUP = 0, -1, -2, -3, -4
 F32, F64 = 1, 2
 MIXED_CENTRAL, MIXED_CELL, MIXED_ZERO = 0, 1, 2
 PSI_SUPERCONSISTENT, PSI_HEUN = 0, 1
-BC_NEUMANN, BC_EXTRAPOLATE = 0, 1
+BC_NEUMANN, BC_EXTRAPOLATE, BC_INFLOW = 0, 1, 2
 AFFINE, STREAM_SIN, VECPOT_SIN, VORTEX, PSEUDO1D, LEVEQUE3D = 1, 2, 3, 4, 5, 6
 
 EXPORTS = ("gals_create", "gals_destroy", "gals_layout", "gals_workspace_bytes",
@@ -37,7 +37,7 @@ EXPORTS = ("gals_create", "gals_destroy", "gals_layout", "gals_workspace_bytes",
            "gals_batch_set_tiles", "gals_batch_get_tiles", "gals_batch_advance",
            "gals_batch_autotune", "gals_checkpoint_bytes", "gals_advance_save",
            "gals_adjoint_workspace_bytes", "gals_adjoint", "gals_adjoint_step",
-           "gals_shape_loss", "gals_set_psi_update")
+           "gals_shape_loss", "gals_set_psi_update", "gals_set_inflow_data")
 
 _lib = None
 
@@ -85,6 +85,7 @@ def lib():
     L.gals_adjoint_step.argtypes = [vp, vp, vp, d, d, vp, vp, vp, vp, sz, vp]
     L.gals_shape_loss.argtypes = [vp, vp, vp, d, PD, vp, vp, sz, vp]
     L.gals_set_psi_update.argtypes = [vp, i]
+    L.gals_set_inflow_data.argtypes = [vp, vp, vp, vp]
     L.gals_last_error.argtypes = []
     L.gals_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -184,6 +185,15 @@ class Grid:
                 torch.from_numpy(np.ascontiguousarray(psi[a])).to(st.dtype))
         return st
 
+    def plane_from_numpy(self, arr):
+        """One device plane (the state layout) from a dense float64 array."""
+        import torch
+        pl = torch.zeros(self.plane, dtype=self.torch_dtype, device=self._dev())
+        shape = tuple(reversed(self.nodes))
+        self._grid_view(pl).copy_(
+            torch.from_numpy(np.ascontiguousarray(np.asarray(arr).reshape(shape))).to(pl.dtype))
+        return pl
+
     def to_numpy(self, state):
         """Dense float64 (phi, psi) arrays from a device state."""
         phi = self._grid_view(state[0]).double().cpu().numpy().ravel()
@@ -208,6 +218,19 @@ class Grid:
         p = np.ascontiguousarray(params, dtype=np.float64)
         ptr = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if p.size else None
         check(lib().gals_set_velocity(self._ctx, int(kind), ptr, p.size, float(period)))
+
+    def set_inflow_data(self, state_b, phit_b):
+        """Dirichlet inflow data for a BC_INFLOW grid: a state (phi, grad
+        planes) and a plane of phi_t, read at boundary nodes for the end
+        time of each step. The grid keeps references to both."""
+        self._check_state(state_b)
+        if (phit_b.dtype != self.torch_dtype or phit_b.numel() < self.plane
+                or phit_b.device != self._dev() or not phit_b.is_contiguous()):
+            raise ValueError("phit_b must be a contiguous plane of the grid's dtype")
+        check(lib().gals_set_inflow_data(self._ctx, ctypes.c_void_p(state_b[0].data_ptr()),
+                                         ctypes.c_void_p(state_b[1].data_ptr()),
+                                         ctypes.c_void_p(phit_b.data_ptr())))
+        self._inflow = (state_b, phit_b)
 
     def set_psi_update(self, mode):
         """PSI_SUPERCONSISTENT (default) or PSI_HEUN for later advances."""

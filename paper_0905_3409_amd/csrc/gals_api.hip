@@ -115,6 +115,7 @@ hipError_t advance_core(const gals_ctx *ctx, void *phi, void *grad, double t0, d
         const double c3 = time_factor(ctx->period, t + 0.5 * dt);
         void **src = bufs[(n - n_begin) & 1], **dst = bufs[(n - n_begin + 1) & 1];
         e = launch_step(ctx, src[0], src[1], dst[0], dst[1], dt, c1, c2, c3, coltab, rowtab, s);
+        if (e == hipSuccess && ctx->inflow) e = launch_inflow(ctx, dst[0], dst[1], c1, dt, s);
         if (e != hipSuccess) return e;
     }
     if ((n_end - n_begin) & 1) {
@@ -197,12 +198,12 @@ int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo,
     if (mixed_mode != GALS_MIXED_CENTRAL && mixed_mode != GALS_MIXED_CELL &&
         mixed_mode != GALS_MIXED_ZERO)
         return fail(GALS_EINVAL, "gals_create: unknown mixed-derivative mode %d", mixed_mode);
-    if (bc != GALS_BC_NEUMANN && bc != GALS_BC_EXTRAPOLATE)
+    if (bc != GALS_BC_NEUMANN && bc != GALS_BC_EXTRAPOLATE && bc != GALS_BC_INFLOW)
         return fail(GALS_EINVAL, "gals_create: unknown boundary treatment %d", bc);
     Geom g;
     memset(&g, 0, sizeof(g));
     g.dim = dim;
-    g.bc = bc;
+    g.bc = bc == GALS_BC_INFLOW ? GALS_BC_NEUMANN : bc;  // feet outside: projected
     int64_t nodes = 1;
     for (int a = 0; a < 3; a++) {
         g.n[a] = 1;
@@ -245,6 +246,7 @@ int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo,
     c->device = device;
     c->g = g;
     c->vel_set = false;
+    c->inflow = bc == GALS_BC_INFLOW;
     *out = c;
     return GALS_OK;
 }
@@ -330,6 +332,23 @@ int gals_set_velocity(gals_ctx *ctx, int kind, const double *params, int64_t npa
     return GALS_OK;
 }
 
+int gals_set_inflow_data(gals_ctx *ctx, const void *phi_b, const void *grad_b,
+                         const void *phit_b)
+{
+    if (!ctx) return fail(GALS_EINVAL, "gals_set_inflow_data: NULL context");
+    if (!ctx->inflow)
+        return fail(GALS_EINVAL, "gals_set_inflow_data: the context was not created with "
+                                 "GALS_BC_INFLOW");
+    if (!phi_b || !grad_b || !phit_b) return fail(GALS_EINVAL, "gals_set_inflow_data: NULL array");
+    const size_t es = elem_size(ctx);
+    if (!aligned(phi_b, es) || !aligned(grad_b, es) || !aligned(phit_b, es))
+        return fail(GALS_EINVAL, "gals_set_inflow_data: misaligned array");
+    ctx->inflow_phi = phi_b;
+    ctx->inflow_grad = grad_b;
+    ctx->inflow_phit = phit_b;
+    return GALS_OK;
+}
+
 int gals_set_psi_update(gals_ctx *ctx, int mode)
 {
     if (!ctx) return fail(GALS_EINVAL, "gals_set_psi_update: NULL context");
@@ -345,6 +364,8 @@ int gals_advance(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int
     if (!ctx) return fail(GALS_EINVAL, "gals_advance: NULL context");
     if (!phi || !grad || !workspace) return fail(GALS_EINVAL, "gals_advance: NULL pointer");
     if (!ctx->vel_set) return fail(GALS_EINVAL, "gals_advance: no velocity set");
+    if (ctx->inflow && !ctx->inflow_phi)
+        return fail(GALS_EINVAL, "gals_advance: GALS_BC_INFLOW without gals_set_inflow_data");
     if (!isfinite(dt) || !(dt > 0.0)) return fail(GALS_EINVAL, "gals_advance: dt must be finite and > 0");
     if (!isfinite(t0)) return fail(GALS_EINVAL, "gals_advance: t0 must be finite");
     if (steps < 0) return fail(GALS_EINVAL, "gals_advance: steps < 0");
@@ -493,6 +514,7 @@ int check_adjoint_ctx(const gals_ctx *ctx, const char *what)
     if (ctx->psi != GALS_PSI_SUPERCONSISTENT)
         return fail(GALS_ENOTSUP, "%s: the adjoint covers the superconsistent gradient update",
                     what);
+    if (ctx->inflow) return fail(GALS_ENOTSUP, "%s: no adjoint of inflow data", what);
     return GALS_OK;
 }
 

@@ -97,6 +97,8 @@ struct gals_ctx {
     double period;
     gals::Vel<float> vf;
     gals::Vel<double> vd;
+    bool inflow;  // GALS_BC_INFLOW: g.bc is GALS_BC_NEUMANN for the feet
+    const void *inflow_phi, *inflow_grad, *inflow_phit;
 };
 
 namespace gals {
@@ -110,6 +112,11 @@ hipError_t launch_step(const gals_ctx *ctx, const void *phi, const void *grad, v
                        const void *coltab, const void *rowtab, hipStream_t s);
 // Per-column / per-row stream-function tables (GALS_VEL_STREAM_SIN only).
 hipError_t launch_stream_tables(const gals_ctx *ctx, void *coltab, void *rowtab, hipStream_t s);
+
+// Dirichlet inflow data after a step of size dt ending at time factor c
+// (kernels_misc.hip).
+hipError_t launch_inflow(const gals_ctx *ctx, void *phi, void *grad, double c, double dt,
+                         hipStream_t s);
 
 // Adjoint of the stream-function step and the shape loss (adjoint.hip).
 // adjoint_blocks: blocks of the adjoint launch (16 partials each).

@@ -47,7 +47,8 @@ def test_create_validation():
     assert _ctx(prec=3)[0] == pkg.EINVAL
     assert _ctx(mixed=7)[0] == pkg.EINVAL
     assert _ctx(mixed=pkg.MIXED_CELL)[0] == pkg.OK
-    assert _ctx(bc=2)[0] == pkg.EINVAL
+    assert _ctx(bc=3)[0] == pkg.EINVAL
+    assert _ctx(bc=pkg.BC_INFLOW)[0] == pkg.OK
     assert _ctx(bc=pkg.BC_EXTRAPOLATE)[0] == pkg.OK
     assert _ctx(device=-2)[0] in (pkg.EINVAL, pkg.EHIP)
     assert _ctx(dim=3, ncell=(2048, 2048, 1024))[0] == pkg.EINVAL  # >= 2^31 nodes
@@ -357,5 +358,32 @@ def test_psi_update_option():
     v = ctypes.c_void_p
     assert L.gals_adjoint_step(c2, v(1 << 30), v(1 << 31), 0.0, 0.01, v(1 << 32), v(1 << 33),
                                v(1 << 34), v(1 << 35), 1 << 30, None) == pkg.ENOTSUP
+    L.gals_destroy(ctx)
+    L.gals_destroy(c2)
+
+
+def test_inflow_data_validation():
+    L = pkg.lib()
+    P = ctypes.POINTER(ctypes.c_double)
+    v = ctypes.c_void_p
+    rc, ctx = _ctx(dim=2, ncell=(8, 8, 1), prec=pkg.F64, bc=pkg.BC_INFLOW)
+    assert rc == pkg.OK
+    assert L.gals_set_velocity(ctx, pkg.AFFINE, np.zeros(8).ctypes.data_as(P), 8, 0.0) == pkg.OK
+    ws = ctypes.c_size_t()
+    L.gals_workspace_bytes(ctx, ctypes.byref(ws))
+    # no data yet
+    assert L.gals_advance(ctx, v(1 << 30), v(1 << 31), 0.0, 0.1, 1, v(1 << 32), ws.value,
+                          None) == pkg.EINVAL
+    assert b"gals_set_inflow_data" in L.gals_last_error()
+    assert L.gals_set_inflow_data(ctx, None, v(1 << 33), v(1 << 34)) == pkg.EINVAL
+    assert L.gals_set_inflow_data(ctx, v((1 << 33) + 4), v(1 << 33), v(1 << 34)) == pkg.EINVAL
+    assert L.gals_set_inflow_data(ctx, v(1 << 35), v(1 << 33), v(1 << 34)) == pkg.OK
+    rc, c2 = _ctx(dim=2, ncell=(8, 8, 1), prec=pkg.F64)
+    assert L.gals_set_inflow_data(c2, v(1 << 35), v(1 << 33), v(1 << 34)) == pkg.EINVAL
+    # no adjoint through inflow data
+    good = np.array([0.01, 1, 2], dtype=np.float64)
+    assert L.gals_set_velocity(ctx, pkg.STREAM_SIN, good.ctypes.data_as(P), 3, 0.0) == pkg.OK
+    assert L.gals_adjoint_step(ctx, v(1 << 30), v(1 << 31), 0.0, 0.01, v(1 << 32), v(1 << 36),
+                               v(1 << 37), v(1 << 38), 1 << 30, None) == pkg.ENOTSUP
     L.gals_destroy(ctx)
     L.gals_destroy(c2)

@@ -1018,3 +1018,23 @@ def test_lte_pseudo1d_orders_with_inflow_data():
     og = observed_orders(hs, epsi)
     assert op[-1] > 3.6 and op[-1] < 4.4, (ephi, op)
     assert og[-1] > 2.6 and og[-1] < 3.4, (epsi, og)
+
+
+def test_inflow_leaves_streamline_faces_alone():
+    """On the unit box every face is a streamline of a sine stream function
+    (v_n = 0 there up to rounding): no node takes inflow data, whatever the
+    data hold, and the advance equals the Neumann one bit for bit."""
+    rng = np.random.default_rng(160)
+    ncell = (20, 17)
+    coords = inputs.node_grid(ncell)
+    phi, psi = inputs.sdf_union(coords, [[0.4, 0.55]], [0.25])
+    params = np.array([0.5, 1, 1, -0.2, 2, 3])
+    N = phi.size
+
+    def garbage(t):
+        return (rng.normal(size=N) * 1e3, rng.normal(size=2 * N) * 1e3,
+                rng.normal(size=N) * 1e3)
+    args = (2, ncell, [0, 0], [1, 1], inputs.STREAM_SIN, params, 1.1, phi, psi, 0.0, 0.02, 6)
+    a = oracle.advance_inflow(*args, garbage)
+    b = oracle.advance(*args)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
