@@ -22,7 +22,7 @@ _LIB_PATH = os.path.join(_HERE, "libgals_oracle.so")
 AFFINE, STREAM_SIN, VECPOT_SIN, VORTEX, PSEUDO1D, LEVEQUE3D = 1, 2, 3, 4, 5, 6
 MIXED_CENTRAL, MIXED_CELL, MIXED_ZERO = 0, 1, 2
 PSI_SUPERCONSISTENT, PSI_HEUN = 0, 1
-BC_NEUMANN, BC_EXTRAPOLATE = 0, 1
+BC_NEUMANN, BC_EXTRAPOLATE, BC_INFLOW_NEUMANN = 0, 1, 3
 
 _lib = None
 

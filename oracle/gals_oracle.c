@@ -585,7 +585,7 @@ static int step_node(const grid_t *g, int kind, const double *params, long np,
     node_coords(g, idx, ijk);
     for (int a = 0; a < d; a++) x[a] = g->lo[a] + (double)ijk[a] * g->h[a];
     if (orc_trace(d, kind, params, np, period, x, t, dt, X, D)) return -1;
-    if (bc == 0) {
+    if (bc == 0 || bc == 3) {
         /* homogeneous Neumann: project the foot onto the domain */
         for (int a = 0; a < d; a++) {
             double top = g->lo[a] + (double)g->nc[a] * g->h[a];
@@ -628,14 +628,175 @@ static int step_node(const grid_t *g, int kind, const double *params, long np,
     return 0;
 }
 
+/* Inflow faces of a boundary node (sec. 4.1: where v . n < 0). The flow
+ * enters through face a when its inward normal component exceeds
+ * INFLOW_THETA max(|v|, h_a / dt), dt the step: along a face that is a
+ * streamline (v_n = 0 analytically) or at a stagnation point the rounding of
+ * v must not decide, and the Dirichlet normal derivative, which divides by
+ * v_n, stays bounded. Returns the number of inflow faces; in[a] marks them. */
+#define INFLOW_THETA 1e-6
+static int inflow_axes(const grid_t *g, const long *ijk, const double *v, double dt, int *in)
+{
+    double speed2 = 0.0;
+    int nin = 0;
+    for (int a = 0; a < g->dim; a++) speed2 += v[a] * v[a];
+    for (int a = 0; a < g->dim; a++) {
+        const double vmin = INFLOW_THETA * fmax(sqrt(speed2), g->h[a] / dt);
+        /* low face: outward normal -e_a, inflow if v_a > 0; high face: v_a < 0 */
+        in[a] = (ijk[a] == 0 && v[a] > vmin) || (ijk[a] == g->nc[a] && v[a] < -vmin);
+        nin += in[a];
+    }
+    return nin;
+}
+
+/* Velocity restricted to the axes tax[0..k-1] of a boundary face: the
+ * components v_T and their derivatives along T, Gs[i*k+j] = d v_{T_j} / d x_{T_i}
+ * (the deformation-matrix convention), at a point whose other coordinates
+ * stay on the face. */
+static int face_velocity(const grid_t *g, int kind, const double *params, long np,
+                         double period, const double *x, double t, const int *tax, int k,
+                         double *vs, double *Gs)
+{
+    double v[MAXD], G[9];
+    if (orc_velocity(g->dim, kind, params, np, period, x, t, v, G)) return -1;
+    for (int i = 0; i < k; i++) {
+        vs[i] = v[tax[i]];
+        for (int j = 0; j < k; j++) Gs[i * k + j] = G[tax[i] * g->dim + tax[j]];
+    }
+    return 0;
+}
+
+/* Homogeneous Neumann inflow (sec. 4.1, eq. Neumann_bc_evolution with zero
+ * prescribed normal derivative): at a boundary node where the flow enters
+ * through the faces marked in[], phi and the gradient along the remaining
+ * (tangential) axes T solve phi_t + v_T . grad_T phi = 0 on the face by a
+ * GA-CIR step of dimension k = |T| (sec. 4, steps 1-3): the superconsistent
+ * Shu-Osher trace with v_T, its foot projected onto the face, the k-cubic
+ * Hermite interpolant of the face data at time t (cross derivative of the
+ * pair of T axes by the context's rule) and psi_T = D grad H. The normal
+ * derivatives are the prescribed zeros. With no tangential axis left (a
+ * corner where the flow enters through every face) phi keeps its value. */
+static int face_node(const grid_t *g, int kind, const double *params, long np, double period,
+                     int mixed_mode, const double *phi, const double *psi, const double *mixed,
+                     double t, double dt, const long *ijk, const int *in, double *phi_new,
+                     double *psi_new)
+{
+    int d = g->dim, k = 0, tax[MAXD];
+    long N = g->nodes, idx = node_index(g, ijk);
+    for (int a = 0; a < d; a++) {
+        psi_new[a] = 0.0;
+        if (!in[a]) tax[k++] = a;
+    }
+    if (k == 0) {
+        *phi_new = phi[idx];
+        return 0;
+    }
+    /* superconsistent Shu-Osher trace on the face (as orc_trace, axes T only) */
+    double x[MAXD], x1[MAXD], x2[MAXD], X[MAXD];
+    double v0[2], v1[2], v2[2], G0[4], G1[4], G2[4], D1[4], D2[4], P1[4], P2[4], D[4];
+    for (int a = 0; a < d; a++) x[a] = g->lo[a] + (double)ijk[a] * g->h[a];
+    for (int a = 0; a < d; a++) x1[a] = x2[a] = X[a] = x[a];
+    if (face_velocity(g, kind, params, np, period, x, t + dt, tax, k, v0, G0)) return -1;
+    for (int i = 0; i < k; i++) x1[tax[i]] = x[tax[i]] - dt * v0[i];
+    for (int i = 0; i < k; i++)
+        for (int j = 0; j < k; j++) D1[i * k + j] = (i == j) - dt * G0[i * k + j];
+    if (face_velocity(g, kind, params, np, period, x1, t, tax, k, v1, G1)) return -1;
+    matmul(k, D1, G1, P1);
+    for (int i = 0; i < k; i++) x2[tax[i]] = x[tax[i]] - dt * (0.25 * v0[i] + 0.25 * v1[i]);
+    for (int i = 0; i < k; i++)
+        for (int j = 0; j < k; j++)
+            D2[i * k + j] = (i == j) - dt * (0.25 * G0[i * k + j] + 0.25 * P1[i * k + j]);
+    if (face_velocity(g, kind, params, np, period, x2, t + 0.5 * dt, tax, k, v2, G2)) return -1;
+    matmul(k, D2, G2, P2);
+    for (int i = 0; i < k; i++)
+        X[tax[i]] = x[tax[i]] - dt * (v0[i] / 6.0 + v1[i] / 6.0 + 2.0 * v2[i] / 3.0);
+    for (int i = 0; i < k; i++)
+        for (int j = 0; j < k; j++)
+            D[i * k + j] = (i == j) - dt * (G0[i * k + j] / 6.0 + P1[i * k + j] / 6.0 +
+                                            2.0 * P2[i * k + j] / 3.0);
+    /* project the foot onto the face; locate it in the face's cells */
+    long cell[MAXD], fullcell[MAXD];
+    double xi_full[MAXD], xi[2], hs[2];
+    int outside[2] = {0, 0};
+    for (int i = 0; i < k; i++) {
+        int a = tax[i];
+        double top = g->lo[a] + (double)g->nc[a] * g->h[a];
+        if (X[a] < g->lo[a]) { X[a] = g->lo[a]; outside[i] = 1; }
+        else if (X[a] > top) { X[a] = top; outside[i] = 1; }
+    }
+    locate(g, X, fullcell, xi_full);
+    for (int i = 0; i < k; i++) {
+        cell[i] = fullcell[tax[i]];
+        xi[i] = xi_full[tax[i]];
+        hs[i] = g->h[tax[i]];
+    }
+    /* face cell data, data[v * 2^k + alpha]: vertex bit i and derivative bit
+     * i along T_i; alpha 3 (k = 2) is the cross derivative of the pair */
+    int nv = 1 << k;
+    double data[16], ga[4], gb[4], cr[4];
+    long pair_plane = 0;
+    if (k == 2) pair_plane = (tax[0] == 0) ? (tax[1] == 1 ? 0 : 1) : 2; /* xy, xz, yz */
+    for (int v = 0; v < nv; v++) {
+        long vijk[MAXD];
+        for (int a = 0; a < d; a++) vijk[a] = ijk[a];
+        for (int i = 0; i < k; i++) vijk[tax[i]] = cell[i] + ((v >> i) & 1);
+        long vi = node_index(g, vijk);
+        data[v * nv + 0] = phi[vi];
+        for (int i = 0; i < k; i++) data[v * nv + (1 << i)] = psi[tax[i] * N + vi];
+        if (k == 2) {
+            ga[v] = psi[tax[0] * N + vi];
+            gb[v] = psi[tax[1] * N + vi];
+            /* approach (A): the 3D mixed plane of the pair, a difference along
+             * the face (2D grids have no pair on a face) */
+            data[v * nv + 3] = (mixed_mode == 0) ? mixed[pair_plane * N + vi] : 0.0;
+        }
+    }
+    if (k == 2 && mixed_mode == 1) {
+        cell_cross(ga, gb, hs[0], hs[1], cr);
+        for (int v = 0; v < 4; v++) data[v * nv + 3] = cr[v];
+    }
+    double val, grad[2];
+    orc_hermite(k, data, hs, xi, &val, grad, NULL);
+    for (int i = 0; i < k; i++)
+        if (outside[i]) grad[i] = 0.0;
+    *phi_new = val;
+    for (int i = 0; i < k; i++) {
+        double s = 0.0;
+        for (int j = 0; j < k; j++) s += D[i * k + j] * grad[j];
+        psi_new[tax[i]] = s;
+    }
+    return 0;
+}
+
+/* bc 3: after a step with projected feet, inflow boundary nodes take the
+ * face scheme's values, computed from the state at time t. */
+static int face_override(const grid_t *g, int kind, const double *params, long np,
+                         double period, int mixed_mode, const double *phi, const double *psi,
+                         const double *mixed, double t, double dt, long idx, double *phi_new,
+                         double *psi_new)
+{
+    long ijk[MAXD];
+    double x[MAXD], v[MAXD], G[9];
+    int in[MAXD], on_boundary = 0;
+    node_coords(g, idx, ijk);
+    for (int a = 0; a < g->dim; a++)
+        if (ijk[a] == 0 || ijk[a] == g->nc[a]) on_boundary = 1;
+    if (!on_boundary) return 0;
+    for (int a = 0; a < g->dim; a++) x[a] = g->lo[a] + (double)ijk[a] * g->h[a];
+    if (orc_velocity(g->dim, kind, params, np, period, x, t + dt, v, G)) return -1;
+    if (inflow_axes(g, ijk, v, dt, in) == 0) return 0;
+    return face_node(g, kind, params, np, period, mixed_mode, phi, psi, mixed, t, dt, ijk, in,
+                     phi_new, psi_new);
+}
+
 int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
                 int kind, const double *params, long nparams, double period,
                 int mixed_mode, int bc, int psi_update, double *phi, double *psi,
                 double t0, double dt, long steps)
 {
     grid_t g;
-    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || steps < 0 || bc < 0 || bc > 1 ||
-        psi_update < 0 || psi_update > 1)
+    if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || steps < 0 || bc < 0 || bc > 3 ||
+        bc == 2 || psi_update < 0 || psi_update > 1)
         return -1;
     long N = g.nodes;
     int nm = (dim == 2) ? 1 : 4;
@@ -651,7 +812,9 @@ int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
         for (long idx = 0; idx < N; idx++) {
             double pn, gn[MAXD];
             if (step_node(&g, kind, params, nparams, period, bc, mixed_mode, psi_update, phi,
-                          psi, mixed, t, dt, idx, &pn, gn)) {
+                          psi, mixed, t, dt, idx, &pn, gn) ||
+                (bc == 3 && face_override(&g, kind, params, nparams, period, mixed_mode, phi,
+                                          psi, mixed, t, dt, idx, &pn, gn))) {
                 bad = 1;
                 continue;
             }
@@ -673,12 +836,8 @@ int orc_advance(int dim, const long *ncell, const double *lo, const double *hi,
  * phi_b, grad_b (dim planes) and phit_b hold the prescribed phi, its
  * gradient and its time derivative at the nodes; where the flow enters
  * through more than one face (edges, corners) every gradient component is
- * taken from grad_b. Other nodes are left as they are. The flow enters
- * through face a when its inward normal component exceeds INFLOW_THETA
- * max(|v|, h_a / dt), dt the step: along a face that is a streamline
- * (v_n = 0 analytically) or at a stagnation point the rounding of v must not
- * decide, and phi_n, which divides by v_n, stays bounded. */
-#define INFLOW_THETA 1e-6
+ * taken from grad_b. Other nodes are left as they are. Inflow faces as in
+ * inflow_axes. */
 int orc_apply_inflow(int dim, const long *ncell, const double *lo, const double *hi,
                      int kind, const double *params, long nparams, double period, double t,
                      double dt, double *phi, double *psi, const double *phi_b,
@@ -701,14 +860,9 @@ int orc_apply_inflow(int dim, const long *ncell, const double *lo, const double 
         if (!on_boundary) continue;
         for (int a = 0; a < dim; a++) x[a] = g.lo[a] + (double)ijk[a] * g.h[a];
         if (orc_velocity(dim, kind, params, nparams, period, x, t, v, G)) { bad = 1; break; }
-        double speed2 = 0.0;
-        for (int a = 0; a < dim; a++) speed2 += v[a] * v[a];
-        for (int a = 0; a < dim; a++) {
-            const double vmin = INFLOW_THETA * fmax(sqrt(speed2), g.h[a] / dt);
-            /* low face: outward normal -e_a, inflow if v_a > 0; high face: v_a < 0 */
-            in[a] = (ijk[a] == 0 && v[a] > vmin) || (ijk[a] == g.nc[a] && v[a] < -vmin);
-            if (in[a]) { nin++; axis = a; }
-        }
+        nin = inflow_axes(&g, ijk, v, dt, in);
+        for (int a = 0; a < dim; a++)
+            if (in[a]) axis = a;
         if (nin == 0) continue;
         phi[idx] = phi_b[idx];
         for (int a = 0; a < dim; a++) psi[a * N + idx] = grad_b[a * N + idx];
@@ -730,7 +884,7 @@ int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *h
 {
     grid_t g;
     if (make_grid(&g, dim, ncell, lo, hi) || !phi || !psi || !nodes || count < 0 ||
-        bc < 0 || bc > 1 || psi_update < 0 || psi_update > 1)
+        bc < 0 || bc > 3 || bc == 2 || psi_update < 0 || psi_update > 1)
         return -1;
     long N = g.nodes;
     int nm = (dim == 2) ? 1 : 4;
@@ -741,6 +895,9 @@ int orc_step_nodes(int dim, const long *ncell, const double *lo, const double *h
         if (nodes[k] < 0 || nodes[k] >= N) { err = -1; break; }
         err = step_node(&g, kind, params, nparams, period, bc, mixed_mode, psi_update, phi,
                         psi, mixed, t, dt, nodes[k], &phi_out[k], &psi_out[k * dim]);
+        if (!err && bc == 3)
+            err = face_override(&g, kind, params, nparams, period, mixed_mode, phi, psi, mixed,
+                                t, dt, nodes[k], &phi_out[k], &psi_out[k * dim]);
     }
     free(mixed);
     return err;

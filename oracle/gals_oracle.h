@@ -35,7 +35,10 @@
  * Mixed-derivative modes (sec. 2.3): 0 central differencing (A), 2 all zero.
  * Boundary treatment of feet outside the domain (bc): 0 homogeneous Neumann
  * (foot projected onto the domain, zero normal derivative), 1 extrapolation
- * of the boundary cell's polynomial.
+ * of the boundary cell's polynomial, 3 as 0, and inflow boundary nodes
+ * follow the homogeneous Neumann condition of sec. 4.1 (eq.
+ * Neumann_bc_evolution): a GA-CIR step of one dimension less on the face,
+ * normal derivative 0.
  */
 #ifndef GALS_ORACLE_H
 #define GALS_ORACLE_H

@@ -1038,3 +1038,209 @@ def test_inflow_leaves_streamline_faces_alone():
     a = oracle.advance_inflow(*args, garbage)
     b = oracle.advance(*args)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------------------
+# Sec. 4.1, eq. Neumann_bc_evolution: homogeneous Neumann inflow by a GA-CIR
+# step of one dimension less on the inflow face
+# ---------------------------------------------------------------------------
+def _affine_foot(b, A, coords, dt, steps):
+    """Foot of n backward RK3 steps of x' = b + A x in closed form: the
+    augmented linear system [x; 1]' = [[A, b], [0, 0]] [x; 1] has the
+    amplification I - dt B + dt^2 B^2/2 - dt^3 B^3/6 per step."""
+    dim = len(coords)
+    B = np.zeros((dim + 1, dim + 1))
+    B[:dim, :dim], B[:dim, dim] = A, b
+    M = np.linalg.matrix_power(_rk3_matrix(B, dt), steps)
+    foot = [M[i, dim] + sum(M[i, j] * coords[j] for j in range(dim)) for i in range(dim)]
+    return foot, M[:dim, :dim]
+
+
+def _face_data(dim, mixed, rng):
+    """Data that do not depend on x (so phi_x = 0 holds everywhere, the
+    homogeneous Neumann condition on the inflow face x = 0), chosen so the
+    cross-derivative rule in use is exact for them."""
+    if dim == 2:
+        c = rng.normal(size=4)
+        return Poly({(0, 0): c[0], (0, 1): c[1], (0, 2): c[2], (0, 3): c[3]})
+    terms = {}
+    for e in itertools.product(range(4), repeat=2):
+        if sum(e) <= 3:
+            if mixed == oracle.MIXED_CELL and e[0] and e[1] and e != (1, 1):
+                continue  # (B) is exact for a constant phi_yz
+            if mixed == oracle.MIXED_ZERO and e[0] and e[1]:
+                continue
+            terms[(0,) + e] = rng.normal()
+    return Poly(terms)
+
+
+@pytest.mark.parametrize("dim,mixed", [(2, oracle.MIXED_CENTRAL), (2, oracle.MIXED_ZERO),
+                                       (3, oracle.MIXED_CENTRAL), (3, oracle.MIXED_CELL),
+                                       (3, oracle.MIXED_ZERO)])
+def test_face_scheme_affine_closed_form(dim, mixed):
+    """v = (0.5, -0.3 + 0.8 y[, -0.2 + 0.6 z], with a y-z coupling for (A)):
+    the flow enters through x = 0 only and the tangential velocity on that
+    face depends on the tangential coordinates alone. For data independent of x the exact discrete result is
+    p(foot) with the closed-form RK3 foot everywhere, inflow face included
+    (its face scheme traces with the same tangential map); psi_x stays 0."""
+    rng = np.random.default_rng(170 + dim + 10 * mixed)
+    n = 10 if dim == 2 else 7
+    ncell = (n,) * dim
+    coords = inputs.node_grid(ncell)
+    p = _face_data(dim, mixed, rng)
+    phi, psi = poly_state(p, coords)
+    b = np.array([0.5, -0.3, -0.2][:dim])
+    A = np.diag([0.0, 0.8, 0.6][:dim])
+    if dim == 3 and mixed == oracle.MIXED_CENTRAL:
+        # a tangential Jacobian that is not symmetric (the psi chain's
+        # transpose shows); the y and z faces stay outflow faces
+        A[1, 2], A[2, 1] = 0.3, 0.2
+    params = inputs.affine_params(b, np.zeros(dim), A)
+    dt, steps = 0.05, 4
+    ph, ps = oracle.advance(dim, ncell, np.zeros(dim), np.ones(dim), inputs.AFFINE, params, 0.0,
+                            phi, psi, 0.0, dt, steps, mixed_mode=mixed,
+                            bc=oracle.BC_INFLOW_NEUMANN)
+    foot, M = _affine_foot(b, A, coords, dt, steps)
+    want_phi = p(*foot)
+    grads = [p.deriv(unit(dim, a))(*foot) for a in range(dim)]
+    want_psi = np.concatenate([sum(M[j, i] * grads[j] for j in range(dim)) for i in range(dim)])
+    assert rel_err(ph, want_phi) < 1e-12
+    assert rel_err(ps, want_psi) < 1e-11
+    assert np.all(ps.reshape(dim, -1)[0, coords[0] == 0.0] == 0.0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_face_scheme_keeps_a_face_without_tangential_flow(dim):
+    """v = (0.5, 2 x[, -1.5 x]) vanishes along x = 0 except for its normal
+    part: there the homogeneous Neumann condition leaves phi_t = 0, so the
+    face nodes keep phi and the tangential gradient, with psi_x = 0. The
+    projection of feet (bc 0), which follows the characteristic from outside
+    the domain, moves them."""
+    rng = np.random.default_rng(180 + dim)
+    n = 12 if dim == 2 else 7
+    ncell = (n,) * dim
+    coords = inputs.node_grid(ncell)
+    p = Poly.random_total_degree(rng, dim, 3)
+    phi, psi = poly_state(p, coords)
+    A = np.zeros((dim, dim))
+    A[1, 0] = 2.0
+    if dim == 3:
+        A[2, 0] = -1.5
+    b = np.zeros(dim)
+    b[0] = 0.5
+    params = inputs.affine_params(b, np.zeros(dim), A)
+    args = (dim, ncell, np.zeros(dim), np.ones(dim), inputs.AFFINE, params, 0.0, phi, psi, 0.0,
+            0.04, 3)
+    ph, ps = oracle.advance(*args, bc=oracle.BC_INFLOW_NEUMANN)
+    face = coords[0] == 0.0
+    ps, psi = ps.reshape(dim, -1), psi.reshape(dim, -1)
+    assert np.max(np.abs(ph[face] - phi[face])) <= 1e-14 * np.max(np.abs(phi))
+    for a in range(1, dim):
+        assert np.max(np.abs(ps[a, face] - psi[a, face])) <= 1e-13 * np.max(np.abs(psi))
+    assert np.all(ps[0, face] == 0.0)
+    pr, _ = oracle.advance(*args, bc=oracle.BC_NEUMANN)
+    assert np.max(np.abs(pr[face] - phi[face])) > 1e-4
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_face_scheme_corner_and_edge(dim):
+    """Constant velocity entering through every low face: at the corner no
+    tangential axis is left, so phi keeps its value and the gradient is 0; in
+    3D with v_z = -0.2 + 0.6 z the edge x = y = 0 is a 1D problem along z, and
+    data p(z) follow the closed-form foot there and everywhere else."""
+    rng = np.random.default_rng(190 + dim)
+    n = 9 if dim == 2 else 6
+    ncell = (n,) * dim
+    coords = inputs.node_grid(ncell)
+    p = Poly.random_total_degree(rng, dim, 3)
+    phi, psi = poly_state(p, coords)
+    b = np.array([0.4, 0.3, 0.2][:dim])
+    params = inputs.affine_params(b, np.zeros(dim), np.zeros((dim, dim)))
+    ph, ps = oracle.advance(dim, ncell, np.zeros(dim), np.ones(dim), inputs.AFFINE, params, 0.0,
+                            phi, psi, 0.0, 0.05, 2, bc=oracle.BC_INFLOW_NEUMANN)
+    assert ph[0] == phi[0]
+    assert np.all(ps.reshape(dim, -1)[:, 0] == 0.0)
+    if dim == 3:
+        pz = Poly({(0, 0, k): c for k, c in enumerate(rng.normal(size=4))})
+        phi, psi = poly_state(pz, coords)
+        b = np.array([0.4, 0.3, -0.2])
+        A = np.diag([0.0, 0.0, 0.6])
+        params = inputs.affine_params(b, np.zeros(3), A)
+        dt, steps = 0.05, 3
+        ph, ps = oracle.advance(3, ncell, np.zeros(3), np.ones(3), inputs.AFFINE, params, 0.0,
+                                phi, psi, 0.0, dt, steps, bc=oracle.BC_INFLOW_NEUMANN)
+        foot, M = _affine_foot(b, A, coords, dt, steps)
+        assert rel_err(ph, pz(*foot)) < 1e-12
+        want_z = pz.deriv(unit(3, 2))(*foot) * M[2, 2]
+        ps = ps.reshape(3, -1)
+        assert rel_err(ps[2], want_z) < 1e-11
+        assert np.max(np.abs(ps[:2])) < 1e-12 * np.max(np.abs(ps[2]))
+        edge = (coords[0] == 0.0) & (coords[1] == 0.0)
+        assert np.all(ps[:2, edge] == 0.0)
+
+
+def test_face_foot_beyond_the_face_is_projected():
+    """A face node whose tangential foot leaves the face through its edge
+    (CFL 1.5 along y, the flow entering through x = 0 and y = 0) takes the
+    value at the edge node, and its tangential derivative along the leaving
+    axis is 0, as feet outside the domain are treated in the full step."""
+    rng = np.random.default_rng(200)
+    n, dt = 8, 0.05
+    ncell = (n, n)
+    coords = inputs.node_grid(ncell)
+    p = Poly.random_total_degree(rng, 2, 3)
+    phi, psi = poly_state(p, coords)
+    b = np.array([0.4, 1.5 * (1.0 / n) / dt])
+    params = inputs.affine_params(b, np.zeros(2), np.zeros((2, 2)))
+    ph, ps = oracle.advance(2, ncell, [0, 0], [1, 1], inputs.AFFINE, params, 0.0, phi, psi, 0.0,
+                            dt, 1, bc=oracle.BC_INFLOW_NEUMANN)
+    ps = ps.reshape(2, -1)
+    node01, node02 = (n + 1), 2 * (n + 1)  # (x=0, y=h), (x=0, y=2h)
+    assert ph[node01] == phi[0]
+    assert ps[0, node01] == 0.0 and ps[1, node01] == 0.0
+    # one cell further up the foot stays on the face: the 1D cubic at y = h/2
+    want = p(0.0, 0.5 / n)
+    assert abs(ph[node02] - want) <= 1e-13
+    assert ps[1, node02] == pytest.approx(p.deriv((0, 1))(0.0, 0.5 / n), rel=1e-12)
+
+
+@pytest.mark.parametrize("mixed", [oracle.MIXED_CENTRAL, oracle.MIXED_CELL])
+def test_face_scheme_reduces_to_the_2d_step(mixed):
+    """A 3D problem whose data and tangential velocity do not depend on x,
+    with the flow entering through x = 0: the face x = 0 follows the 2D
+    GA-CIR scheme on (y, z) (itself pinned above), here with a
+    time-modulated affine field and smooth non-polynomial data. The y and z
+    faces are outflow faces, so no 2D foot leaves the face."""
+    nc3, nc2 = (5, 9, 8), (9, 8)
+    c3, c2 = inputs.node_grid(nc3), inputs.node_grid(nc2)
+
+    def q(y, z):
+        return np.sin(2.1 * y + 0.7) * np.cos(1.3 * z) + 0.4 * y * z * z
+
+    def qy(y, z):
+        return 2.1 * np.cos(2.1 * y + 0.7) * np.cos(1.3 * z) + 0.4 * z * z
+
+    def qz(y, z):
+        return -1.3 * np.sin(2.1 * y + 0.7) * np.sin(1.3 * z) + 0.8 * y * z
+
+    phi3 = q(c3[1], c3[2])
+    psi3 = np.concatenate([np.zeros_like(phi3), qy(c3[1], c3[2]), qz(c3[1], c3[2])])
+    phi2 = q(c2[0], c2[1])
+    psi2 = np.concatenate([qy(c2[0], c2[1]), qz(c2[0], c2[1])])
+    A2 = np.array([[0.8, 0.3], [0.2, 0.6]])
+    A3 = np.zeros((3, 3))
+    A3[1:, 1:] = A2
+    p3 = inputs.affine_params([0.5, -0.3, -0.2], np.zeros(3), A3)
+    p2 = inputs.affine_params([-0.3, -0.2], np.zeros(2), A2)
+    t0, dt, steps, period = 0.02, 0.04, 5, 3.0
+    ph3, ps3 = oracle.advance(3, nc3, np.zeros(3), np.ones(3), inputs.AFFINE, p3, period, phi3,
+                              psi3, t0, dt, steps, mixed_mode=mixed, bc=oracle.BC_INFLOW_NEUMANN)
+    ph2, ps2 = oracle.advance(2, nc2, np.zeros(2), np.ones(2), inputs.AFFINE, p2, period, phi2,
+                              psi2, t0, dt, steps, mixed_mode=mixed)
+    face = c3[0] == 0.0
+    ps3 = ps3.reshape(3, -1)
+    ps2 = ps2.reshape(2, -1)
+    assert rel_err(ph3[face], ph2) <= 1e-14
+    assert rel_err(ps3[1, face], ps2[0]) <= 1e-13
+    assert rel_err(ps3[2, face], ps2[1]) <= 1e-13
+    assert np.all(ps3[0, face] == 0.0)
