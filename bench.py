@@ -23,7 +23,9 @@ sweep (each segment recomputed from its checkpoint, then 20 adjoint steps).
 
 --workload variants times the 2048^2 advance (FP32) for each cross-derivative
 reconstruction (central (A), cell-based (B), zero) with the superconsistent
-and with Heun's gradient update.
+and with Heun's gradient update, and on a box shifted by 0.1 (the flow then
+enters through parts of every face) with the projection of feet alone,
+Dirichlet inflow data, and the homogeneous Neumann face scheme.
 
 --workload volume runs the 3D deformation test of the paper's volume-loss
 tables (LeVeque's field x cos(pi t / 2.5), dt = h, to t = 2.5; a sphere and a
@@ -539,6 +541,39 @@ def bench_variants(args):
     for m in names.values():
         table[f"{m}, heun / superconsistent time"] = (table[f"{m}, heun"]["step_us"] /
                                                      table[f"{m}, superconsistent"]["step_us"])
+    # inflow boundary conditions (sec. 4.1): the same field on a box shifted
+    # so that the flow enters through parts of every face
+    lo, hi = (-0.1, -0.1), (1.1, 1.1)
+    coords = inputs.node_grid(w["ncell"], lo, hi)
+    phi_b, psi_b = inputs.sdf_union(coords, w["centres"], w["radii"])
+    bcs = {pkg.BC_NEUMANN: "projection", pkg.BC_INFLOW: "Dirichlet data",
+           pkg.BC_INFLOW_NEUMANN: "Neumann face scheme"}
+    for bc, bname in bcs.items():
+        g = pkg.Grid(w["ncell"], lo, hi, dtype="float32", bc=bc)
+        g.set_velocity(w["kind"], w["params"], w["period"])
+        ref = g.from_numpy(phi_b, psi_b)
+        st = ref.clone()
+        if bc == pkg.BC_INFLOW:
+            data = ref.clone()  # fixed data: the initial state, phi_t = 0
+            phit = torch.zeros(g.plane, dtype=torch.float32, device="cuda")
+            g.set_inflow_data(data, phit)
+        times = []
+        for k in range(args.warmup + args.steps):
+            st.copy_(ref)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            g.advance(st, 0.0, w["dt"], inner)
+            b.record(s)
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(a.elapsed_time(b))
+        us = float(np.mean(times)) * 1e3 / inner
+        table[f"inflow box, {bname}"] = {"step_us": us, "node_updates_per_s": nodes / (us * 1e-6)}
+        log(f"inflow box {bname:20s}: {us:6.2f} us/step")
+        del g, ref, st
+    for bname in ("Dirichlet data", "Neumann face scheme"):
+        table[f"inflow box, {bname} / projection time"] = (
+            table[f"inflow box, {bname}"]["step_us"] / table["inflow box, projection"]["step_us"])
     main = table["cell-based (B), superconsistent"]
     flops = nodes * VARIANT_B_FLOPS_PER_NODE / (main["step_us"] * 1e-6) / 1e12
     line = {

@@ -81,8 +81,20 @@ enum { GALS_PSI_SUPERCONSISTENT = 0, GALS_PSI_HEUN = 1 };
  * cell out, e.g. a rotation at CFL > 1 in the corners). GALS_BC_INFLOW:
  * Dirichlet inflow data (sec. 4.1) from gals_set_inflow_data at boundary
  * nodes where the flow enters, feet outside the domain projected as with
- * GALS_BC_NEUMANN. */
-enum { GALS_BC_NEUMANN = 0, GALS_BC_EXTRAPOLATE = 1, GALS_BC_INFLOW = 2 };
+ * GALS_BC_NEUMANN. GALS_BC_INFLOW_NEUMANN: the homogeneous Neumann inflow
+ * condition of sec. 4.1 (eq. Neumann_bc_evolution, zero normal derivative):
+ * feet projected as with GALS_BC_NEUMANN, and boundary nodes where the flow
+ * enters take phi and the tangential gradient from a GA-CIR step of one
+ * dimension less on the face (tangential velocity, face data at the start of
+ * the step, the context's cross-derivative rule, superconsistent gradient
+ * update), normal derivatives 0; a corner entered through every face keeps
+ * its value. Inflow faces as for gals_set_inflow_data. Single grids only. */
+enum {
+    GALS_BC_NEUMANN = 0,
+    GALS_BC_EXTRAPOLATE = 1,
+    GALS_BC_INFLOW = 2,
+    GALS_BC_INFLOW_NEUMANN = 3
+};
 
 /* Velocity fields v(x,t) = c(t) v_s(x), c(t) = cos(pi t / period) when
  * period > 0, else 1. Parameter vectors (FP64):

@@ -27,7 +27,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOTSUP = 0, -1, -2, -3, -4
 F32, F64 = 1, 2
 MIXED_CENTRAL, MIXED_CELL, MIXED_ZERO = 0, 1, 2
 PSI_SUPERCONSISTENT, PSI_HEUN = 0, 1
-BC_NEUMANN, BC_EXTRAPOLATE, BC_INFLOW = 0, 1, 2
+BC_NEUMANN, BC_EXTRAPOLATE, BC_INFLOW, BC_INFLOW_NEUMANN = 0, 1, 2, 3
 AFFINE, STREAM_SIN, VECPOT_SIN, VORTEX, PSEUDO1D, LEVEQUE3D = 1, 2, 3, 4, 5, 6
 
 EXPORTS = ("gals_create", "gals_destroy", "gals_layout", "gals_workspace_bytes",

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgals.so")
-SOURCES = ["gals_api.hip", "gals_batch_api.hip", "kernels_step.hip", "kernels_misc.hip",
+SOURCES = ["gals_api.hip", "gals_batch_api.hip", "kernels_step.hip", "kernels_misc.hip", "boundary.hip",
            "batch.hip", "adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

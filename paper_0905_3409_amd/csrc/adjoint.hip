@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint2d_stream(
             v1b[a] = v0b[a];
             v2b[a] = -dtT * T(2.0 / 3.0) * Xb[a];
         }
-        const double x0 = g.lo[0] + double(i) * g.h[0], y0 = g.lo[1] + double(j) * g.h[1];
+        const double x0 = node_coord(g.lo[0], i, g.h[0]), y0 = node_coord(g.lo[1], j, g.h[1]);
         T sx[4], cx[4], sy[4], cy[4], t3[4];
         T sb[16];
 #pragma unroll

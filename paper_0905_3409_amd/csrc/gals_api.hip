@@ -116,6 +116,8 @@ hipError_t advance_core(const gals_ctx *ctx, void *phi, void *grad, double t0, d
         void **src = bufs[(n - n_begin) & 1], **dst = bufs[(n - n_begin + 1) & 1];
         e = launch_step(ctx, src[0], src[1], dst[0], dst[1], dt, c1, c2, c3, coltab, rowtab, s);
         if (e == hipSuccess && ctx->inflow) e = launch_inflow(ctx, dst[0], dst[1], c1, dt, s);
+        if (e == hipSuccess && ctx->face)
+            e = launch_face(ctx, src[0], src[1], dst[0], dst[1], dt, c1, c2, c3, s);
         if (e != hipSuccess) return e;
     }
     if ((n_end - n_begin) & 1) {
@@ -198,12 +200,12 @@ int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo,
     if (mixed_mode != GALS_MIXED_CENTRAL && mixed_mode != GALS_MIXED_CELL &&
         mixed_mode != GALS_MIXED_ZERO)
         return fail(GALS_EINVAL, "gals_create: unknown mixed-derivative mode %d", mixed_mode);
-    if (bc != GALS_BC_NEUMANN && bc != GALS_BC_EXTRAPOLATE && bc != GALS_BC_INFLOW)
+    if (bc < GALS_BC_NEUMANN || bc > GALS_BC_INFLOW_NEUMANN)
         return fail(GALS_EINVAL, "gals_create: unknown boundary treatment %d", bc);
     Geom g;
     memset(&g, 0, sizeof(g));
     g.dim = dim;
-    g.bc = bc == GALS_BC_INFLOW ? GALS_BC_NEUMANN : bc;  // feet outside: projected
+    g.bc = bc == GALS_BC_EXTRAPOLATE ? bc : GALS_BC_NEUMANN;  // feet outside: projected
     int64_t nodes = 1;
     for (int a = 0; a < 3; a++) {
         g.n[a] = 1;
@@ -220,7 +222,7 @@ int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo,
         g.lo[a] = lo[a];
         g.h[a] = (hi[a] - lo[a]) / double(ncell[a]);
         g.inv_h[a] = 1.0 / g.h[a];
-        g.top[a] = g.lo[a] + double(g.nc[a]) * g.h[a];
+        g.top[a] = node_coord(g.lo[a], g.nc[a], g.h[a]);
         nodes *= g.n[a];
         if (nodes >= (int64_t(1) << 31))
             return fail(GALS_EINVAL, "gals_create: more than 2^31 - 1 nodes");
@@ -247,6 +249,7 @@ int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo,
     c->g = g;
     c->vel_set = false;
     c->inflow = bc == GALS_BC_INFLOW;
+    c->face = bc == GALS_BC_INFLOW_NEUMANN;
     *out = c;
     return GALS_OK;
 }
@@ -514,7 +517,8 @@ int check_adjoint_ctx(const gals_ctx *ctx, const char *what)
     if (ctx->psi != GALS_PSI_SUPERCONSISTENT)
         return fail(GALS_ENOTSUP, "%s: the adjoint covers the superconsistent gradient update",
                     what);
-    if (ctx->inflow) return fail(GALS_ENOTSUP, "%s: no adjoint of inflow data", what);
+    if (ctx->inflow || ctx->face)
+        return fail(GALS_ENOTSUP, "%s: no adjoint of the inflow boundary conditions", what);
     return GALS_OK;
 }
 

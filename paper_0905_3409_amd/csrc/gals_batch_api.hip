@@ -289,7 +289,7 @@ int gals_batch_create(gals_batch **out, int64_t nprob, const int64_t *ncell, con
             g.lo[a] = l;
             g.h[a] = (h - l) / double(nc);
             g.inv_h[a] = 1.0 / g.h[a];
-            g.top[a] = l + double(nc) * g.h[a];
+            g.top[a] = node_coord(l, nc, g.h[a]);
         }
         g.nodes = int64_t(g.n[0]) * g.n[1];
         g.pitch = round_up(g.n[0], 64);

@@ -34,6 +34,16 @@ struct Geom {
     int64_t nodes;   // n[0]*n[1]*n[2]
 };
 
+// Coordinate of node i along an axis: lo + i h with the product rounded before
+// the sum, never fused, on the host and in every kernel alike. A fused value
+// can land one ulp beyond top (computed the same way), and a foot at that
+// node would then count as outside the domain.
+__host__ __device__ inline double node_coord(double lo, int64_t i, double h)
+{
+#pragma clang fp contract(off)
+    return lo + double(i) * h;
+}
+
 // Velocity parameters in the arithmetic type T, passed by value to kernels.
 // Stream-function modes are folded into dense 4x4 tables over (m,n) so that
 // every loop is fully unrolled with compile-time wavenumbers.
@@ -98,6 +108,7 @@ struct gals_ctx {
     gals::Vel<float> vf;
     gals::Vel<double> vd;
     bool inflow;  // GALS_BC_INFLOW: g.bc is GALS_BC_NEUMANN for the feet
+    bool face;    // GALS_BC_INFLOW_NEUMANN: likewise, plus the face scheme
     const void *inflow_phi, *inflow_grad, *inflow_phit;
 };
 
@@ -113,10 +124,13 @@ hipError_t launch_step(const gals_ctx *ctx, const void *phi, const void *grad, v
 // Per-column / per-row stream-function tables (GALS_VEL_STREAM_SIN only).
 hipError_t launch_stream_tables(const gals_ctx *ctx, void *coltab, void *rowtab, hipStream_t s);
 
-// Dirichlet inflow data after a step of size dt ending at time factor c
-// (kernels_misc.hip).
+// Inflow boundary conditions after a step of size dt (boundary.hip):
+// Dirichlet data at time factor c, and homogeneous Neumann inflow by the face
+// scheme from the state before the step (sphi, sgrad) into the stepped one.
 hipError_t launch_inflow(const gals_ctx *ctx, void *phi, void *grad, double c, double dt,
                          hipStream_t s);
+hipError_t launch_face(const gals_ctx *ctx, const void *sphi, const void *sgrad, void *dphi,
+                       void *dgrad, double dt, double c1, double c2, double c3, hipStream_t s);
 
 // Adjoint of the stream-function step and the shape loss (adjoint.hip).
 // adjoint_blocks: blocks of the adjoint launch (16 partials each).

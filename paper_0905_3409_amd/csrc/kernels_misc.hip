@@ -151,107 +151,6 @@ hipError_t launch_norms(const gals_ctx *ctx, const void *phi, const void *grad,
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Dirichlet inflow data (sec. 4.1) at boundary nodes where v(x, t) enters the
-// domain: phi prescribed, tangential gradient prescribed, normal derivative
-// from the equation phi_t + v . grad phi = 0 (all components prescribed where
-// the flow enters through several faces). One thread per node; interior
-// nodes return at once.
-// ---------------------------------------------------------------------------
-template <typename T, int D, int KIND>
-__global__ __launch_bounds__(kBlock) void k_inflow(Geom g, Vel<T> p, T c, double dt,
-                                                   T *__restrict__ phi,
-                                                   T *__restrict__ grad,
-                                                   const T *__restrict__ phi_b,
-                                                   const T *__restrict__ grad_b,
-                                                   const T *__restrict__ phit_b)
-{
-    const int64_t id = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (id >= g.nodes) return;
-    int ijk[D];
-    int64_t r = id;
-    bool edge = false;
-#pragma unroll
-    for (int a = 0; a < D; a++) {
-        ijk[a] = int(r % g.n[a]);
-        r /= g.n[a];
-        edge = edge || ijk[a] == 0 || ijk[a] == g.nc[a];
-    }
-    if (!edge) return;
-    double x[D];
-#pragma unroll
-    for (int a = 0; a < D; a++) x[a] = g.lo[a] + double(ijk[a]) * g.h[a];
-    T v[D], A[D * D];
-    velocity<T, D, KIND>(p, x, c, v, A);
-    // the flow enters through face a when its inward normal component exceeds
-    // kInflowTheta max(|v|, h_a / dt): rounding must not decide on a face that
-    // is a streamline or at a stagnation point, and the normal derivative,
-    // divided by v_n, stays bounded
-    constexpr T kInflowTheta = T(1e-6);
-    T speed2 = T(0);
-#pragma unroll
-    for (int a = 0; a < D; a++) speed2 += v[a] * v[a];
-    const T speed = sqrt(speed2);
-    int nin = 0, axis = 0;
-#pragma unroll
-    for (int a = 0; a < D; a++) {
-        const T vmin = kInflowTheta * fmax(speed, T(g.h[a] / dt));
-        // low face: outward normal -e_a, inflow if v_a > 0; high face: v_a < 0
-        const bool in = (ijk[a] == 0 && v[a] > vmin) || (ijk[a] == g.nc[a] && v[a] < -vmin);
-        if (in) {
-            nin++;
-            axis = a;
-        }
-    }
-    if (nin == 0) return;
-    const int64_t o = node_offset(g, id);
-    phi[o] = phi_b[o];
-    T s = phit_b[o];
-#pragma unroll
-    for (int a = 0; a < D; a++) {
-        const T ga = grad_b[a * g.plane + o];
-        grad[a * g.plane + o] = ga;
-        if (a != axis) s += v[a] * ga;
-    }
-    if (nin == 1) grad[axis * g.plane + o] = -s / v[axis];
-}
-
-template <typename T>
-static hipError_t inflow_typed(const gals_ctx *ctx, const Vel<T> &p, void *phi, void *grad,
-                               double c, double dt, hipStream_t s)
-{
-    const dim3 grid(unsigned((ctx->g.nodes + kBlock - 1) / kBlock)), block(kBlock);
-    const T cc = T(c);
-    T *ph = (T *)phi, *gr = (T *)grad;
-    const T *pb = (const T *)ctx->inflow_phi, *gb = (const T *)ctx->inflow_grad,
-            *tb = (const T *)ctx->inflow_phit;
-#define GALS_INFLOW(D, K)                                                                         \
-    case D * 16 + K:                                                                              \
-        hipLaunchKernelGGL((k_inflow<T, D, K>), grid, block, 0, s, ctx->g, p, cc, dt, ph, gr, pb, \
-                           gb, tb);                                                               \
-        break;
-    switch (ctx->dim * 16 + ctx->vel_kind) {
-        GALS_INFLOW(2, GALS_VEL_AFFINE)
-        GALS_INFLOW(2, GALS_VEL_STREAM_SIN)
-        GALS_INFLOW(2, GALS_VEL_VORTEX)
-        GALS_INFLOW(2, GALS_VEL_PSEUDO1D)
-        GALS_INFLOW(3, GALS_VEL_AFFINE)
-        GALS_INFLOW(3, GALS_VEL_VECPOT_SIN)
-        GALS_INFLOW(3, GALS_VEL_LEVEQUE3D)
-    default:
-        return hipErrorInvalidValue;
-    }
-#undef GALS_INFLOW
-    return hipGetLastError();
-}
-
-hipError_t launch_inflow(const gals_ctx *ctx, void *phi, void *grad, double c, double dt,
-                         hipStream_t s)
-{
-    return ctx->prec == GALS_F32 ? inflow_typed<float>(ctx, ctx->vf, phi, grad, c, dt, s)
-                                 : inflow_typed<double>(ctx, ctx->vd, phi, grad, c, dt, s);
-}
-
 // max over nodes of |v(x_node, t)|, c = c(t)
 template <typename T, int D, int KIND>
 __global__ __launch_bounds__(kBlock) void k_max_speed(Geom g, Vel<T> p, T c,
@@ -266,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_max_speed(Geom g, Vel<T> p, T c,
         for (int a = 0; a < D; a++) {
             const int64_t ia = r % g.n[a];
             r /= g.n[a];
-            x[a] = g.lo[a] + double(ia) * g.h[a];
+            x[a] = node_coord(g.lo[a], ia, g.h[a]);
         }
         T v[D], J[D * D];
         velocity<T, D, KIND>(p, x, c, v, J);

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st
     const int i = int(id - unsigned(j) * nx);
     const T *gx = grad, *gy = grad + g.plane;
 
-    const double x[2] = {g.lo[0] + double(i) * g.h[0], g.lo[1] + double(j) * g.h[1]};
+    const double x[2] = {node_coord(g.lo[0], i, g.h[0]), node_coord(g.lo[1], j, g.h[1])};
     double X[2];
     T J[4];  // superconsistent Jacobian, or (Heun) grad v at the node
     trace<T, 2, KIND, PSI == GALS_PSI_SUPERCONSISTENT>(p, st, dt, x, X, J);
@@ -77,8 +77,8 @@ __global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st
     const int j = int(row - unsigned(k) * ny);
     const T *gx = grad, *gy = grad + g.plane, *gz = grad + 2 * g.plane;
 
-    const double x[3] = {g.lo[0] + double(i) * g.h[0], g.lo[1] + double(j) * g.h[1],
-                         g.lo[2] + double(k) * g.h[2]};
+    const double x[3] = {node_coord(g.lo[0], i, g.h[0]), node_coord(g.lo[1], j, g.h[1]),
+                         node_coord(g.lo[2], k, g.h[2])};
     double X[3];
     T J[9];
     trace<T, 3, KIND, PSI == GALS_PSI_SUPERCONSISTENT>(p, st, dt, x, X, J);

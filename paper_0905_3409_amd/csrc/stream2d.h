@@ -21,7 +21,7 @@ __device__ __forceinline__ void stream_table_entry(const Geom &g, const double (
 {
     const int nx = g.n[0], ny = g.n[1];
     if (id < nx) {
-        const double x = g.lo[0] + double(id) * g.h[0];
+        const double x = node_coord(g.lo[0], id, g.h[0]);
         double s[4], c[4];
         for (int m = 0; m < 4; m++) sincospi(double(m + 1) * x, &s[m], &c[m]);
         for (int a = 0; a < 5; a++)
@@ -39,7 +39,7 @@ __device__ __forceinline__ void stream_table_entry(const Geom &g, const double (
             }
     } else if (id < nx + ny) {
         const int j = id - nx;
-        const double y = g.lo[1] + double(j) * g.h[1];
+        const double y = node_coord(g.lo[1], j, g.h[1]);
         for (int n = 0; n < 4; n++) {
             double s, c;
             sincospi(double(n + 1) * y, &s, &c);
@@ -160,7 +160,7 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
         }
         stream_jet(u, y, jet);
     }
-    const double x0 = g.lo[0] + double(i) * g.h[0], y0 = g.lo[1] + double(j) * g.h[1];
+    const double x0 = node_coord(g.lo[0], i, g.h[0]), y0 = node_coord(g.lo[1], j, g.h[1]);
     const T dtT = T(dt);
     // stage 1 at the node, time t + dt
     from_stream(jet.d10, jet.d01, jet.d20, jet.d11, jet.d02, st.c1, f.v0, f.A0);
@@ -221,7 +221,7 @@ __device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Sta
     const int64_t o = int64_t(j) * g.pitch + i;
     phi_o[o] = H;
     if constexpr (PSI == GALS_PSI_HEUN) {
-        const double x0 = g.lo[0] + double(i) * g.h[0], y0 = g.lo[1] + double(j) * g.h[1];
+        const double x0 = node_coord(g.lo[0], i, g.h[0]), y0 = node_coord(g.lo[1], j, g.h[1]);
         T vf[2], Af[4], ps[2];
         const T gH[2] = {Hx, Hy};
         stream_stage<T, TAYLOR>(p, f.jet, x0, y0, T((f.s[0] - double(i)) * g.h[0]),

@@ -47,8 +47,10 @@ def test_create_validation():
     assert _ctx(prec=3)[0] == pkg.EINVAL
     assert _ctx(mixed=7)[0] == pkg.EINVAL
     assert _ctx(mixed=pkg.MIXED_CELL)[0] == pkg.OK
-    assert _ctx(bc=3)[0] == pkg.EINVAL
+    assert _ctx(bc=4)[0] == pkg.EINVAL
+    assert _ctx(bc=-1)[0] == pkg.EINVAL
     assert _ctx(bc=pkg.BC_INFLOW)[0] == pkg.OK
+    assert _ctx(bc=pkg.BC_INFLOW_NEUMANN)[0] == pkg.OK
     assert _ctx(bc=pkg.BC_EXTRAPOLATE)[0] == pkg.OK
     assert _ctx(device=-2)[0] in (pkg.EINVAL, pkg.EHIP)
     assert _ctx(dim=3, ncell=(2048, 2048, 1024))[0] == pkg.EINVAL  # >= 2^31 nodes
@@ -186,7 +188,8 @@ def test_batch_create_validation():
     assert _batch([(8, 8)], prec=5)[0] == pkg.EINVAL
     assert _batch([(8, 8)], mixed=3)[0] == pkg.EINVAL
     assert _batch([(8, 8)], mixed=pkg.MIXED_CELL)[0] == pkg.OK
-    assert _batch([(8, 8)], bc=3)[0] == pkg.EINVAL
+    assert _batch([(8, 8)], bc=pkg.BC_INFLOW)[0] == pkg.EINVAL  # single grids only
+    assert _batch([(8, 8)], bc=pkg.BC_INFLOW_NEUMANN)[0] == pkg.EINVAL
     assert _batch([(8, 8)], device=-3)[0] == pkg.EINVAL
     assert _batch([(8, 8)], lo=[0.0, 1.0], hi=[1.0, 1.0])[0] == pkg.EINVAL
     assert _batch([(40000, 20000)])[0] == pkg.EINVAL  # plane of 2 GiB or more
@@ -385,5 +388,11 @@ def test_inflow_data_validation():
     assert L.gals_set_velocity(ctx, pkg.STREAM_SIN, good.ctypes.data_as(P), 3, 0.0) == pkg.OK
     assert L.gals_adjoint_step(ctx, v(1 << 30), v(1 << 31), 0.0, 0.01, v(1 << 32), v(1 << 36),
                                v(1 << 37), v(1 << 38), 1 << 30, None) == pkg.ENOTSUP
+    rc, c3 = _ctx(dim=2, ncell=(8, 8, 1), prec=pkg.F64, bc=pkg.BC_INFLOW_NEUMANN)
+    assert L.gals_set_velocity(c3, pkg.STREAM_SIN, good.ctypes.data_as(P), 3, 0.0) == pkg.OK
+    assert L.gals_adjoint_step(c3, v(1 << 30), v(1 << 31), 0.0, 0.01, v(1 << 32), v(1 << 36),
+                               v(1 << 37), v(1 << 38), 1 << 30, None) == pkg.ENOTSUP
+    assert L.gals_set_inflow_data(c3, v(1 << 35), v(1 << 33), v(1 << 34)) == pkg.EINVAL
+    L.gals_destroy(c3)
     L.gals_destroy(ctx)
     L.gals_destroy(c2)

@@ -251,3 +251,143 @@ def test_streamline_faces_take_no_data(dtype):
     a = gpu_inflow(*args, garbage, dtype=dtype)
     b = gpu_advance(*args, dtype=dtype)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------------------
+# Homogeneous Neumann inflow by the face scheme (eq. Neumann_bc_evolution)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mixed,psi", [(pkg.MIXED_CENTRAL, pkg.PSI_SUPERCONSISTENT),
+                                       (pkg.MIXED_CELL, pkg.PSI_SUPERCONSISTENT),
+                                       (pkg.MIXED_ZERO, pkg.PSI_HEUN)])
+@pytest.mark.parametrize("name,dim,kind,params,period,ncell,lo,hi,dt,steps", CASES)
+def test_face_scheme_fp64_matches_oracle(name, dim, kind, params, period, ncell, lo, hi, dt,
+                                         steps, mixed, psi):
+    from gpu_util import gpu_advance, oracle_advance
+    from test_gpu_step import _random_smooth_state
+    rng = np.random.default_rng(len(name) * 7 + dim)
+    phi0, psi0 = _random_smooth_state(rng, ncell, lo, hi)
+    print(f"face scheme {name} mixed={mixed} psi={psi}", flush=True)
+    args = (dim, ncell, lo, hi, kind, params, period, phi0, psi0, 0.05, dt, steps)
+    g = gpu_advance(*args, dtype="float64", mixed=mixed, psi=psi, bc=pkg.BC_INFLOW_NEUMANN)
+    o = oracle_advance(*args, mixed=mixed, psi=psi, bc=pkg.BC_INFLOW_NEUMANN)
+    hmin = min((hi[a] - lo[a]) / ncell[a] for a in range(dim))
+    print(f"  phi {rel(g[0], o[0]):.2e} psi/scale {rel_psi(g[1], o[1], o[0], hmin):.2e}")
+    assert rel(g[0], o[0]) <= TOL64
+    assert rel_psi(g[1], o[1], o[0], hmin) <= TOL64
+    # the face scheme changed the inflow boundary
+    n = oracle_advance(*args, mixed=mixed, psi=psi)
+    assert rel(n[0], o[0]) > 1e-8
+
+
+@pytest.mark.parametrize("mixed", [pkg.MIXED_CENTRAL, pkg.MIXED_CELL])
+def test_face_scheme_affine_closed_form_on_gpu(mixed):
+    """3D, v = (0.5, -0.3 + 0.8 y + 0.3 z, -0.2 + 0.2 y + 0.6 z) (A) or its
+    diagonal part (B), data independent of x for which the cross-derivative
+    rule is exact: every node, inflow face included, equals p at the
+    closed-form RK3 foot of the augmented affine system."""
+    rng = np.random.default_rng(210 + mixed)
+    ncell = (7, 8, 6)
+    coords = inputs.node_grid(ncell)
+    c = rng.normal(size=10)
+    if mixed == pkg.MIXED_CENTRAL:
+        A = np.array([[0.0, 0.0, 0.0], [0.0, 0.8, 0.3], [0.0, 0.2, 0.6]])
+
+        def p(y, z):
+            return (c[0] + c[1] * y + c[2] * z + c[3] * y * y + c[4] * y * z + c[5] * z * z
+                    + c[6] * y ** 3 + c[7] * y * y * z + c[8] * y * z * z + c[9] * z ** 3)
+
+        def grad(y, z):
+            return (c[1] + 2 * c[3] * y + c[4] * z + 3 * c[6] * y * y + 2 * c[7] * y * z
+                    + c[8] * z * z,
+                    c[2] + c[4] * y + 2 * c[5] * z + c[7] * y * y + 2 * c[8] * y * z
+                    + 3 * c[9] * z * z)
+    else:
+        A = np.diag([0.0, 0.8, 0.6])
+
+        def p(y, z):  # constant cross derivative: (B) is exact
+            return c[0] + c[1] * y + c[2] * z + c[3] * y * y + c[4] * y * z + c[5] * z * z \
+                + c[6] * y ** 3 + c[9] * z ** 3
+
+        def grad(y, z):
+            return (c[1] + 2 * c[3] * y + c[4] * z + 3 * c[6] * y * y,
+                    c[2] + c[4] * y + 2 * c[5] * z + 3 * c[9] * z * z)
+    b = np.array([0.5, -0.3, -0.2])
+    gy, gz = grad(coords[1], coords[2])
+    phi0 = p(coords[1], coords[2])
+    psi0 = np.concatenate([np.zeros_like(phi0), gy, gz])
+    dt, steps = 0.05, 4
+    from gpu_util import gpu_advance
+    g = gpu_advance(3, ncell, (0.0,) * 3, (1.0,) * 3, inputs.AFFINE,
+                    inputs.affine_params(b, np.zeros(3), A), 0.0, phi0, psi0, 0.0, dt, steps,
+                    dtype="float64", mixed=mixed, bc=pkg.BC_INFLOW_NEUMANN)
+    Baug = np.zeros((4, 4))
+    Baug[:3, :3], Baug[:3, 3] = A, b
+    R = np.eye(4) - dt * Baug + dt * dt * Baug @ Baug / 2 - dt ** 3 * Baug @ Baug @ Baug / 6
+    M = np.linalg.matrix_power(R, steps)
+    foot = [M[i, 3] + sum(M[i, j] * coords[j] for j in range(3)) for i in range(3)]
+    fy, fz = grad(foot[1], foot[2])
+    want_psi = np.concatenate([np.zeros_like(phi0), M[1, 1] * fy + M[2, 1] * fz,
+                               M[1, 2] * fy + M[2, 2] * fz])
+    print(f"closed form: phi {rel(g[0], p(foot[1], foot[2])):.2e} psi {rel(g[1], want_psi):.2e}")
+    assert rel(g[0], p(foot[1], foot[2])) <= 1e-12
+    assert rel(g[1], want_psi) <= 1e-11
+
+
+@pytest.mark.parametrize("n", [96, 300])
+def test_face_scheme_fp32_stream(n):
+    """FP32 stream-function step followed by the face kernel against the
+    FP64 oracle (n = 300 mixes the Taylor and exact stages)."""
+    from gpu_util import gpu_advance
+    from test_gpu_step import _random_smooth_state
+    ncell, lo, hi = (n, n), (-0.1, -0.1), (1.1, 1.1)
+    phi0, psi0 = _random_smooth_state(np.random.default_rng(n), ncell, lo, hi)
+    params = np.array([0.4, 1, 2, -0.25, 3, 1, 0.1, 2, 2])
+    dt, steps = 0.6 * (1.2 / n), 6
+    args = (2, ncell, lo, hi, inputs.STREAM_SIN, params, 1.5, phi0, psi0, 0.0, dt, steps)
+    g = gpu_advance(*args, dtype="float32", bc=pkg.BC_INFLOW_NEUMANN)
+    o = oracle.advance(*args, bc=oracle.BC_INFLOW_NEUMANN)
+    tp, tg = fp32_tolerances(o[0], o[1], 1.2 / n, steps)
+    print(f"n={n}: phi {rel(g[0], o[0]):.2e} (tol {tp:.1e}) psi {rel(g[1], o[1]):.2e} "
+          f"(tol {tg:.1e})")
+    assert rel(g[0], o[0]) <= tp
+    assert rel(g[1], o[1]) <= tg
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_face_scheme_large_grid_sampled(dtype):
+    """1024^2 sine stream field on a shifted box (flow enters through parts
+    of every face): one step, every boundary node (4096 of them, 17 blocks
+    with a ragged last one) against the oracle node by node, and sampled
+    interior nodes."""
+    import torch
+    n = 1024
+    ncell, lo, hi = (n, n), (-0.1, -0.05), (1.1, 1.15)
+    w = inputs.stream_circles(seed=5, n=n, steps=n // 2)
+    coords = inputs.node_grid(ncell, lo, hi)
+    phi0, psi0 = inputs.sdf_union(coords, [[0.3, 0.4], [0.7, 0.6]], [0.2, 0.15])
+    gr = pkg.Grid(ncell, lo, hi, dtype=dtype, bc=pkg.BC_INFLOW_NEUMANN, device=0)
+    gr.set_velocity(w["kind"], w["params"], w["period"])
+    st = gr.from_numpy(phi0, psi0)
+    dt = 1.2 / n
+    gr.advance(st, 0.1, dt, 1)
+    torch.cuda.synchronize()
+    g = gr.to_numpy(st)
+    ix, iy = np.arange(n + 1), np.arange(n + 1)
+    bnd = np.unique(np.concatenate([iy * (n + 1), iy * (n + 1) + n, ix, n * (n + 1) + ix]))
+    rng = np.random.default_rng(3)
+    nodes = np.concatenate([bnd, rng.integers(0, (n + 1) ** 2, size=2000)])
+    po, go = oracle.step_nodes(2, ncell, lo, hi, w["kind"], w["params"], w["period"], phi0, psi0,
+                               0.1, dt, nodes, bc=oracle.BC_INFLOW_NEUMANN)
+    gpsi = g[1].reshape(2, -1)[:, nodes].T
+    if dtype == "float64":
+        tp = tg = 1e-12
+    else:
+        tp, tg = fp32_tolerances(po, go, 1.2 / n, 1)
+    e_phi = np.max(np.abs(g[0][nodes] - po)) / np.max(np.abs(po))
+    e_psi = np.max(np.abs(gpsi - go)) / max(np.max(np.abs(go)), np.max(np.abs(po)) * n / 1.2)
+    print(f"{dtype}: {bnd.size} boundary nodes, phi {e_phi:.2e} psi {e_psi:.2e}")
+    assert e_phi <= tp
+    assert e_psi <= tg
+    # some boundary nodes took the face scheme: psi normal component exactly 0
+    # where the oracle says so
+    assert np.sum(go[: bnd.size] == 0.0) > 100
