@@ -62,6 +62,22 @@ BYTES_PER_NODE = 24  # FP32 state: 3 planes read once + 3 planes written once
 # The cell-based (B) cross derivatives replace the 8 flops of the central
 # differences by 4 edge differences and 4 weighted vertex sums (28 flops).
 VARIANT_B_FLOPS_PER_NODE = ALG_FLOPS_PER_NODE - 8 + 28
+# FP32 3D step, 6-mode vector potential, central cross derivatives, as the
+# kernel formulates it (FMA = 2): velocity and Jacobian at the node from the
+# per-axis tables (multiples 36, 6 modes x 59, scaling 12: 402) and at the two
+# off-node stages with the angles shifted by angle addition (shift 36,
+# multiples 36, modes 354, scaling 12: 438 each), FP64 stage positions 30,
+# Jacobian chain 216, foot and split 30, cross derivatives 120, Hermite
+# weights 60, tricubic value and gradient 384, gradient update 18.
+FLOPS_PER_NODE_3D = 402 + 2 * 438 + 30 + 216 + 30 + 120 + 60 + 384 + 18
+BYTES_PER_NODE_3D = 32  # FP32 state: 4 planes read once + 4 planes written once
+# Bandwidth probe (rigid rotation, the cheapest field): the affine velocity
+# costs 12 flops a stage in 2D and 24 in 3D, the rest is the step as above:
+# 2D 3 x 12 + chain 80 + foot 18 + cross 8 + weights 40 + bicubic 80 + update 6;
+# 3D 3 x 24 + positions 30 + chain 216 + foot 30 + cross 120 + weights 60 +
+# tricubic 384 + update 18.
+PROBE_FLOPS_PER_NODE_2D = 3 * 12 + 80 + 18 + 8 + 40 + 80 + 6
+PROBE_FLOPS_PER_NODE_3D = 3 * 24 + 30 + 216 + 30 + 120 + 60 + 384 + 18
 
 
 def log(msg):
@@ -120,7 +136,9 @@ def main():
     ap.add_argument("--inner", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched", "adjoint", "variants", "volume"],
+    ap.add_argument("--workload",
+                    choices=["single", "batched", "adjoint", "variants", "volume", "3d",
+                             "probe"],
                     default="single")
     ap.add_argument("--tiles", default="",
                     help="batched only: wave widths per size class, e.g. 64,0,16,64, "
@@ -149,6 +167,10 @@ def main():
         return bench_variants(args)
     if args.workload == "volume":
         return bench_volume(args)
+    if args.workload == "3d":
+        return bench_3d(args)
+    if args.workload == "probe":
+        return bench_probe(args)
     dev = torch.device("cuda", 0)
     w = inputs.stream_circles()
     inner = args.inner or w["steps"]
@@ -645,6 +667,170 @@ def bench_volume(args):
                    "grids": golden["n"], "volume": "prod(h) sum H_eps(-phi), eps = 1.5 h"},
         "volume_table": table,
         "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_probe(args):
+    """Labelled bandwidth probe, not one of the workloads: rigid rotation (the
+    cheapest velocity) on working sets far beyond the 256 MB Infinity Cache,
+    2D 8192^2 and 3D 384^3, FP32."""
+    import numpy as np
+    import torch
+
+    import paper_0905_3409_amd as pkg
+    from paper_0905_3409_amd import inputs
+
+    table = {}
+    cases = [("2d", (8192, 8192), 32, BYTES_PER_NODE, PROBE_FLOPS_PER_NODE_2D),
+             ("3d", (384, 384, 384), 16, BYTES_PER_NODE_3D, PROBE_FLOPS_PER_NODE_3D)]
+    for name, ncell, steps, bpn, fpn in cases:
+        dim = len(ncell)
+        A = np.zeros((dim, dim))
+        A[0, 1], A[1, 0] = -2.0 * np.pi, 2.0 * np.pi
+        params = inputs.affine_params(np.zeros(dim), np.full(dim, 0.5), A)
+        dt = 0.9 / ncell[0] / (np.pi * np.sqrt(2.0))  # CFL 0.9 at the corners
+        g = pkg.Grid(ncell, dtype="float32")
+        g.set_velocity(inputs.AFFINE, params, 0.0)
+        st = torch.zeros((1 + dim, g.plane), dtype=torch.float32, device="cuda")
+        st[0].normal_()
+        st[1:].normal_()
+        g.advance(st, 0.0, dt, 2)  # warm-up
+        times = []
+        for _ in range(max(args.steps, 1)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            g.advance(st, 0.0, dt, steps)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        us = float(np.median(times)) * 1e3 / steps
+        nodes = int(np.prod([c + 1 for c in ncell]))
+        gbps = nodes * bpn / (us * 1e-6) / 1e9
+        tflops = nodes * fpn / (us * 1e-6) / 1e12
+        table[name] = {"cells": list(ncell), "step_us": us,
+                       "node_updates_per_s": nodes / (us * 1e-6),
+                       "state_bytes": int(st.numel() * 4), "hbm_gbps_algorithmic": gbps,
+                       "hbm_frac": gbps / HBM_PEAK_GBPS, "tflops": tflops,
+                       "valu_frac": tflops / VALU_F32_PEAK_TFLOPS}
+        log(f"probe {name} {ncell}: {us:.1f} us/step, {nodes / us / 1e3:.1f} G node-upd/s, "
+            f"{gbps:.0f} GB/s algorithmic ({gbps / HBM_PEAK_GBPS:.2f} of HBM), "
+            f"{tflops:.1f} TFLOP/s ({tflops / VALU_F32_PEAK_TFLOPS:.2f} of VALU)")
+        del g, st
+        torch.cuda.empty_cache()
+    main = table["2d"]
+    line = {
+        "metric": "bandwidth probe (not a workload): rigid rotation, FP32, 2D 8192^2 and "
+                  "3D 384^3", "value": main["node_updates_per_s"], "unit": "node-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": main["step_us"] / 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "probe: rotation about the centre at 2 pi per unit time, CFL 0.9 "
+                               "at the corners, random state"},
+        "probe": table,
+        "roofline": {"bound": "hbm", "achieved": main["hbm_gbps_algorithmic"],
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": main["hbm_frac"],
+                     "traffic": None, "kernel": "k_step2d<float, AFFINE, CENTRAL>"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_3d(args):
+    import numpy as np
+    import torch
+
+    import paper_0905_3409_amd as pkg
+    from paper_0905_3409_amd import inputs
+
+    w = inputs.vecpot_spheres()
+    inner = args.inner or w["steps"]
+    n = w["ncell"][0]
+    h = 1.0 / n
+    nodes = (n + 1) ** 3
+    eps, band = 1.5 * h, 3 * h
+    log(f"workload {w['name']} {n}^3 cells, {inner} steps/bench step, dt={w['dt']:.6g}")
+    pts = inputs.random_points(7, 1_000_000, 3)
+
+    def run(dtype, steps, timed):
+        g = pkg.Grid(w["ncell"], w["lo"], w["hi"], dtype=dtype)
+        g.set_velocity(w["kind"], w["params"], w["period"])
+        ref = g.from_numpy(w["phi0"], w["psi0"])
+        st = ref.clone()
+        times = []
+        for k in range(timed):
+            st.copy_(ref)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            g.advance(st, 0.0, w["dt"], steps)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        return g, st, ref, times
+
+    if args.profile:
+        steps = args.inner or 8
+        g, st, _, _ = run("float32", steps, 1)
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        torch.empty_like(src).copy_(src)  # plain copy: reads and writes exactly 256 MiB
+        torch.cuda.synchronize()
+        log(f"profile: {steps} FP32 steps on {nodes} nodes, then a {nbytes} B device copy")
+        return 0
+    g32, st32, ref32, _ = run("float32", min(inner, 8), max(args.warmup, 1))  # warm-up
+    del g32, st32, ref32
+    torch.cuda.empty_cache()
+    g32, st32, ref32, times = run("float32", inner, args.steps)
+    adv_ms = float(np.mean(times))
+    kernel_us = adv_ms * 1e3 / inner
+    value = nodes * inner / (adv_ms * 1e-3)
+    n32 = g32.norms(st32, ref32, eps, band)
+    # curvature at 1e6 points at t = T
+    dpts = torch.from_numpy(np.ascontiguousarray(pts)).to("cuda")
+    g32.eval_points(st32, dpts)  # warm-up
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    g32.eval_points(st32, dpts)
+    b.record()
+    torch.cuda.synchronize()
+    eval_ms = a.elapsed_time(b)
+    log(f"fp32: advance {adv_ms:.1f} ms, step kernel {kernel_us:.1f} us, "
+        f"{value / 1e9:.2f} G node-upd/s, L1 shape err {n32[2]:.3e}; 1e6 point evals "
+        f"{eval_ms:.3f} ms")
+    del g32, st32, ref32
+    torch.cuda.empty_cache()
+    res = {}
+    if not args.no_fp64:
+        g64, st64, ref64, t64 = run("float64", inner, 1)
+        n64 = g64.norms(st64, ref64, eps, band)
+        res["fp64"] = {"value": nodes * inner / (t64[0] * 1e-3), "advance_ms": t64[0],
+                       "l1_shape_error": n64[2], "linf_band_error": n64[3]}
+        res["l1_shape_error_ratio_fp32_over_fp64"] = n32[2] / n64[2] if n64[2] > 0 else None
+        log(f"fp64: advance {t64[0]:.1f} ms, {res['fp64']['value'] / 1e9:.2f} G node-upd/s, "
+            f"L1 shape err {n64[2]:.3e}")
+        del g64, st64, ref64
+    gbps = nodes * BYTES_PER_NODE_3D / (kernel_us * 1e-6) / 1e9
+    tflops = nodes * FLOPS_PER_NODE_3D / (kernel_us * 1e-6) / 1e12
+    line = {
+        "metric": "GALS node-updates/s, 3D tricubic step (256^3, FP32)", "value": value,
+        "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": adv_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "vecpot_spheres: 256^3 cells, 8 seeded spheres, curl of a "
+                               "6-mode sine vector potential x cos(pi t/3), 512 steps, CFL 0.9",
+                   "time_steps_per_step": inner, "seed": w["seed"],
+                   "curvature_points": int(pts.shape[0])},
+        "fp32_l1_shape_error": n32[2], "fp32_linf_band_error": n32[3],
+        "eval_points_ms": eval_ms,
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": VALU_F32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / VALU_F32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_step3d_vecpot<float, CENTRAL, shift, superconsistent>",
+                     "flops_per_launch": nodes * FLOPS_PER_NODE_3D, "avg_launch_us": kernel_us,
+                     "hbm_gbps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS},
+        "cpu_baseline": None,
+        **res,
     }
     print(json.dumps(line), flush=True)
     return 0

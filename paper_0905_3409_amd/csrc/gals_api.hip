@@ -54,9 +54,15 @@ size_t rowtab_offset(const gals_ctx *c)
     return coltab_offset(c) + align256(size_t(kJet) * size_t(c->g.n[0]) * elem_size(c));
 }
 
-size_t workspace_bytes(const gals_ctx *c)
+size_t axistab_offset(const gals_ctx *c)
 {
     return rowtab_offset(c) + align256(size_t(kJet) * size_t(c->g.n[1]) * elem_size(c));
+}
+
+size_t workspace_bytes(const gals_ctx *c)
+{
+    const size_t axis = 2 * size_t(c->g.n[0] + c->g.n[1] + c->g.n[2]) * elem_size(c);
+    return axistab_offset(c) + align256(axis);
 }
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb)
@@ -88,8 +94,10 @@ double time_factor(double period, double t) { return period > 0.0 ? cos(M_PI * t
 // Stream-function tables into the workspace (sine stream functions only).
 hipError_t launch_tables(const gals_ctx *ctx, void *workspace, hipStream_t s)
 {
-    if (ctx->vel_kind != GALS_VEL_STREAM_SIN) return hipSuccess;
     char *ws = (char *)workspace;
+    if (ctx->dim == 3 && ctx->vel_kind == GALS_VEL_VECPOT_SIN)
+        return launch_axis_tables(ctx, ws + axistab_offset(ctx), s);
+    if (ctx->vel_kind != GALS_VEL_STREAM_SIN) return hipSuccess;
     return launch_stream_tables(ctx, ws + coltab_offset(ctx), ws + rowtab_offset(ctx), s);
 }
 
@@ -106,6 +114,8 @@ hipError_t advance_core(const gals_ctx *ctx, void *phi, void *grad, double t0, d
     if (ctx->vel_kind == GALS_VEL_STREAM_SIN) {
         coltab = ws + coltab_offset(ctx);
         rowtab = ws + rowtab_offset(ctx);
+    } else if (ctx->dim == 3 && ctx->vel_kind == GALS_VEL_VECPOT_SIN) {
+        coltab = ws + axistab_offset(ctx);  // the per-axis sin/cos table
     }
     hipError_t e = hipSuccess;
     for (int64_t n = n_begin; n < n_end; n++) {

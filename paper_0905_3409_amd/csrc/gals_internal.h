@@ -123,6 +123,9 @@ hipError_t launch_step(const gals_ctx *ctx, const void *phi, const void *grad, v
                        const void *coltab, const void *rowtab, hipStream_t s);
 // Per-column / per-row stream-function tables (GALS_VEL_STREAM_SIN only).
 hipError_t launch_stream_tables(const gals_ctx *ctx, void *coltab, void *rowtab, hipStream_t s);
+// sin(pi x), cos(pi x) at the node coordinates of each axis (x, then y, then
+// z; one pair per node) for 3D sine vector potentials (kernels_step.hip).
+hipError_t launch_axis_tables(const gals_ctx *ctx, void *tab, hipStream_t s);
 
 // Inflow boundary conditions after a step of size dt (boundary.hip):
 // Dirichlet data at time factor c, and homogeneous Neumann inflow by the face

@@ -62,26 +62,15 @@ __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st
     }
 }
 
+// The part of a 3D step after the trace: boundary treatment of the foot,
+// split, 64-value gather, tricubic value and gradient, gradient update.
 template <typename T, int KIND, int MIX, int PSI>
-__global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st, double dt,
-                                                   const T *__restrict__ phi,
-                                                   const T *__restrict__ grad,
-                                                   T *__restrict__ phi_o, T *__restrict__ grad_o)
+__device__ __forceinline__ void finish3d(const Geom &g, const Vel<T> &p, const Stage<T> &st,
+                                         double dt, int i, int j, int k, double *X, const T *J,
+                                         const T *__restrict__ phi, const T *__restrict__ grad,
+                                         T *__restrict__ phi_o, T *__restrict__ grad_o)
 {
-    const unsigned id = blockIdx.x * kBlock + threadIdx.x;
-    if (id >= unsigned(g.nodes)) return;
-    const unsigned nx = unsigned(g.n[0]), ny = unsigned(g.n[1]);
-    const unsigned row = id / nx;
-    const int i = int(id - row * nx);
-    const int k = int(row / ny);
-    const int j = int(row - unsigned(k) * ny);
     const T *gx = grad, *gy = grad + g.plane, *gz = grad + 2 * g.plane;
-
-    const double x[3] = {node_coord(g.lo[0], i, g.h[0]), node_coord(g.lo[1], j, g.h[1]),
-                         node_coord(g.lo[2], k, g.h[2])};
-    double X[3];
-    T J[9];
-    trace<T, 3, KIND, PSI == GALS_PSI_SUPERCONSISTENT>(p, st, dt, x, X, J);
     const unsigned out = project_foot<3>(g, X);
 
     int cell[3];
@@ -116,6 +105,163 @@ __global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st
         grad_o[g.plane + o] = J[1] * Hx + J[4] * Hy + J[7] * Hz;
         grad_o[2 * g.plane + o] = J[2] * Hx + J[5] * Hy + J[8] * Hz;
     }
+}
+
+template <typename T, int KIND, int MIX, int PSI>
+__global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st, double dt,
+                                                   const T *__restrict__ phi,
+                                                   const T *__restrict__ grad,
+                                                   T *__restrict__ phi_o, T *__restrict__ grad_o)
+{
+    const unsigned id = blockIdx.x * kBlock + threadIdx.x;
+    if (id >= unsigned(g.nodes)) return;
+    const unsigned nx = unsigned(g.n[0]), ny = unsigned(g.n[1]);
+    const unsigned row = id / nx;
+    const int i = int(id - row * nx);
+    const int k = int(row / ny);
+    const int j = int(row - unsigned(k) * ny);
+
+    const double x[3] = {node_coord(g.lo[0], i, g.h[0]), node_coord(g.lo[1], j, g.h[1]),
+                         node_coord(g.lo[2], k, g.h[2])};
+    double X[3];
+    T J[9];
+    trace<T, 3, KIND, PSI == GALS_PSI_SUPERCONSISTENT>(p, st, dt, x, X, J);
+    finish3d<T, KIND, MIX, PSI>(g, p, st, dt, i, j, k, X, J, phi, grad, phi_o, grad_o);
+}
+
+// ---------------------------------------------------------------------------
+// Sine vector potentials in 3D: sin(pi x) and cos(pi x) of every node
+// coordinate come from per-axis tables (FP64-built, one pair per node along
+// each axis); the three stages take the multiples of the node's angles, and
+// in FP32 (SHIFT) the two off-node stages shift them by angle addition
+// whenever every offset is below kShiftMax / pi, instead of evaluating sin
+// and cos at the stage points. The mode sums are those of vel_vecpot.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axis_tables(Geom g, T *__restrict__ tab)
+{
+    const int id = int(blockIdx.x) * kBlock + int(threadIdx.x);
+    int r = id, a = 0;
+    while (a < 3 && r >= g.n[a]) r -= g.n[a++];
+    if (a >= 3) return;
+    double s, c;
+    sincospi(node_coord(g.lo[a], r, g.h[a]), &s, &c);
+    tab[2 * id] = T(s);
+    tab[2 * id + 1] = T(c);
+}
+
+// Velocity at one stage point from the multiples of each axis: through LDS
+// (LDS, the FP32 kernel) or by per-lane selects.
+template <typename T, bool LDS>
+__device__ __forceinline__ void modes_at(const Vel<T> &p, T (*tab)[kBlock], const T *sx,
+                                         const T *cx, const T *sy, const T *cy, const T *sz,
+                                         const T *cz, T cf, T *v, T *A)
+{
+    if constexpr (LDS) {
+        const int tid = int(threadIdx.x);
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            tab[r][tid] = sx[r];
+            tab[4 + r][tid] = cx[r];
+            tab[8 + r][tid] = sy[r];
+            tab[12 + r][tid] = cy[r];
+            tab[16 + r][tid] = sz[r];
+            tab[20 + r][tid] = cz[r];
+        }
+        vecpot_modes_lds(p, tab, tid, cf, v, A);  // each thread reads only its own column
+    } else {
+        vecpot_modes(p, sx, cx, sy, cy, sz, cz, cf, v, A);
+    }
+}
+
+template <typename T, bool SHIFT, bool LDS>
+__device__ __forceinline__ void stage_vecpot(const Vel<T> &p, T (*tab)[kBlock], const T *s1,
+                                             const T *c1, const double *x, const double *xs,
+                                             T cf, T *v, T *A)
+{
+    T sx[4], cx[4], sy[4], cy[4], sz[4], cz[4];
+    bool near = SHIFT;
+    T d[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        d[a] = T(xs[a] - x[a]);
+        near = near && fabs(d[a]) <= T(kShiftMax / kPi);
+    }
+    if (near) {
+        T s[3], c[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) shifted_sincos(s1[a], c1[a], d[a], s[a], c[a]);
+        multiples_from(s[0], c[0], sx, cx);
+        multiples_from(s[1], c[1], sy, cy);
+        multiples_from(s[2], c[2], sz, cz);
+    } else {
+        sincos_multiples(T(xs[0]), sx, cx);
+        sincos_multiples(T(xs[1]), sy, cy);
+        sincos_multiples(T(xs[2]), sz, cz);
+    }
+    modes_at<T, LDS>(p, tab, sx, cx, sy, cy, sz, cz, cf, v, A);
+}
+
+// Five waves per SIMD for the FP32 superconsistent kernel: about 93 VGPRs
+// without spills (six waves would spill); the FP64 and Heun kernels need more
+// registers and keep the compiler's choice.
+template <typename T, int MIX, bool SHIFT, int PSI>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    sizeof(T) == 4 && PSI == GALS_PSI_SUPERCONSISTENT ? 5 : 1))) void k_step3d_vecpot(
+    Geom g, Vel<T> p, Stage<T> st,
+                                                          double dt, const T *__restrict__ tab,
+                                                          const T *__restrict__ phi,
+                                                          const T *__restrict__ grad,
+                                                          T *__restrict__ phi_o,
+                                                          T *__restrict__ grad_o)
+{
+    constexpr bool LDS = sizeof(T) == 4;
+    __shared__ T tab_s[LDS ? 24 : 1][kBlock];
+    const unsigned id = blockIdx.x * kBlock + threadIdx.x;
+    if (id >= unsigned(g.nodes)) return;
+    const unsigned nx = unsigned(g.n[0]), ny = unsigned(g.n[1]);
+    const unsigned row = id / nx;
+    const int i = int(id - row * nx);
+    const int k = int(row / ny);
+    const int j = int(row - unsigned(k) * ny);
+
+    const double x[3] = {node_coord(g.lo[0], i, g.h[0]), node_coord(g.lo[1], j, g.h[1]),
+                         node_coord(g.lo[2], k, g.h[2])};
+    const int64_t ti[3] = {i, int64_t(g.n[0]) + j, int64_t(g.n[0]) + g.n[1] + k};
+    T s1[3], c1[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        s1[a] = tab[2 * ti[a]];
+        c1[a] = tab[2 * ti[a] + 1];
+    }
+    T v0[3], A0[9], v1[3], A1[9], v2[3], A2[9];
+    {
+        T sx[4], cx[4], sy[4], cy[4], sz[4], cz[4];
+        multiples_from(s1[0], c1[0], sx, cx);
+        multiples_from(s1[1], c1[1], sy, cy);
+        multiples_from(s1[2], c1[2], sz, cz);
+        modes_at<T, LDS>(p, tab_s, sx, cx, sy, cy, sz, cz, st.c1, v0, A0);  // v(x, t + dt)
+    }
+    double x1[3], x2[3], X[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) x1[a] = x[a] - dt * double(v0[a]);
+    stage_vecpot<T, SHIFT, LDS>(p, tab_s, s1, c1, x, x1, st.c2, v1, A1);  // v(x1, t)
+#pragma unroll
+    for (int a = 0; a < 3; a++) x2[a] = x[a] - dt * (0.25 * double(v0[a]) + 0.25 * double(v1[a]));
+    stage_vecpot<T, SHIFT, LDS>(p, tab_s, s1, c1, x, x2, st.c3, v2, A2);  // v(x2, t + dt/2)
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+        X[a] = x[a] - dt * (double(v0[a]) * (1.0 / 6.0) + double(v1[a]) * (1.0 / 6.0) +
+                            double(v2[a]) * (2.0 / 3.0));
+    T J[9];
+    if constexpr (PSI == GALS_PSI_SUPERCONSISTENT) {
+        jacobian_chain<T, 3>(A0, A1, A2, T(dt), J);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 9; q++) J[q] = A0[q];
+    }
+    finish3d<T, GALS_VEL_VECPOT_SIN, MIX, PSI>(g, p, st, dt, i, j, k, X, J, phi, grad, phi_o,
+                                              grad_o);
 }
 
 // ---------------------------------------------------------------------------
@@ -174,6 +320,32 @@ static hipError_t launch_stream(const gals_ctx *ctx, const Vel<T> &p, const void
     const dim3 grid((tiles + 7u) / 8u * 8u);
     hipLaunchKernelGGL((k_step2d_stream<T, MIX, sizeof(T) == 4, PSI>), grid, dim3(64, 4), 0, s,
                        ctx->g, p, st, dt, (const T *)coltab, (const T *)rowtab, (const T *)phi,
+                       (const T *)grad, (T *)phi_o, (T *)grad_o);
+    return hipGetLastError();
+}
+
+hipError_t launch_axis_tables(const gals_ctx *ctx, void *tab, hipStream_t s)
+{
+    const int count = ctx->g.n[0] + ctx->g.n[1] + ctx->g.n[2];
+    const unsigned blocks = unsigned((count + kBlock - 1) / kBlock);
+    if (ctx->prec == GALS_F32)
+        hipLaunchKernelGGL(k_axis_tables<float>, dim3(blocks), dim3(kBlock), 0, s, ctx->g,
+                           (float *)tab);
+    else
+        hipLaunchKernelGGL(k_axis_tables<double>, dim3(blocks), dim3(kBlock), 0, s, ctx->g,
+                           (double *)tab);
+    return hipGetLastError();
+}
+
+template <typename T, int MIX, int PSI>
+static hipError_t launch_vecpot(const gals_ctx *ctx, const Vel<T> &p, const void *phi,
+                                const void *grad, void *phi_o, void *grad_o, double dt,
+                                double c1, double c2, double c3, const void *tab, hipStream_t s)
+{
+    const Stage<T> st{T(c1), T(c2), T(c3)};
+    const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_step3d_vecpot<T, MIX, sizeof(T) == 4, PSI>), dim3(blocks),
+                       dim3(kBlock), 0, s, ctx->g, p, st, dt, (const T *)tab, (const T *)phi,
                        (const T *)grad, (T *)phi_o, (T *)grad_o);
     return hipGetLastError();
 }
@@ -245,8 +417,15 @@ hipError_t launch_step(const gals_ctx *ctx, const void *phi, const void *grad, v
                        const void *coltab, const void *rowtab, hipStream_t s)
 {
     const bool stream = ctx->vel_kind == GALS_VEL_STREAM_SIN && coltab && rowtab;
+    const bool vecpot = ctx->dim == 3 && ctx->vel_kind == GALS_VEL_VECPOT_SIN && coltab;
     return with_modes(ctx->mixed, ctx->psi, [&](auto mix, auto psi) -> hipError_t {
         constexpr int MIX = decltype(mix)::value, PSI = decltype(psi)::value;
+        if (vecpot)
+            return ctx->prec == GALS_F32
+                       ? launch_vecpot<float, MIX, PSI>(ctx, ctx->vf, phi, grad, phi_o, grad_o,
+                                                        dt, c1, c2, c3, coltab, s)
+                       : launch_vecpot<double, MIX, PSI>(ctx, ctx->vd, phi, grad, phi_o, grad_o,
+                                                         dt, c1, c2, c3, coltab, s);
         if (stream)
             return ctx->prec == GALS_F32
                        ? launch_stream<float, MIX, PSI>(ctx, ctx->vf, phi, grad, phi_o, grad_o,

@@ -32,6 +32,36 @@ __device__ __forceinline__ void sincos_multiples(T x, T s[4], T c[4])
     c[3] = t * c[2] - c[1];
 }
 
+// The same multiples from sin(pi x), cos(pi x) already known.
+template <typename T>
+__device__ __forceinline__ void multiples_from(T s1, T c1, T s[4], T c[4])
+{
+    s[0] = s1;
+    c[0] = c1;
+    const T t = T(2) * c1;
+    s[1] = t * s[0];
+    c[1] = t * c[0] - T(1);
+    s[2] = t * s[1] - s[0];
+    c[2] = t * c[1] - c[0];
+    s[3] = t * s[2] - s[1];
+    c[3] = t * c[2] - c[1];
+}
+
+// sin(pi (x + d)), cos(pi (x + d)) from s1 = sin(pi x), c1 = cos(pi x) by
+// angle addition, with sin(pi d) and cos(pi d) from their Taylor series: for
+// |pi d| <= kShiftMax the dropped terms are below 3e-9 (sine) and 3e-11
+// (cosine), far under FP32 rounding.
+constexpr double kShiftMax = 0.05;
+template <typename T>
+__device__ __forceinline__ void shifted_sincos(T s1, T c1, T d, T &s, T &c)
+{
+    const T a = T(kPi) * d, a2 = a * a;
+    const T sd = a * (T(1) - a2 * T(1.0 / 6.0));
+    const T cd = T(1) - a2 * (T(0.5) - a2 * T(1.0 / 24.0));
+    s = s1 * cd + c1 * sd;
+    c = c1 * cd - s1 * sd;
+}
+
 template <typename T>
 __device__ __forceinline__ T pick4(const T a[4], int i)
 {
@@ -131,12 +161,10 @@ __device__ __forceinline__ void vel_pseudo1d(const double *x, T c, T *v, T *J)
 //   vpc[6..20] = az LM, ay LN, az MM, ay MN, az MN, ay NN, ax LN, az LL,
 //                ax MN, ax NN, az LN, ay LL, ax LM, ay LM, ax MM
 template <typename T>
-__device__ __forceinline__ void vel_vecpot(const Vel<T> &p, const double *x, T c, T *v, T *J)
+__device__ __forceinline__ void vecpot_modes(const Vel<T> &p, const T *sx, const T *cx,
+                                             const T *sy, const T *cy, const T *sz, const T *cz,
+                                             T c, T *v, T *J)
 {
-    T sx[4], cx[4], sy[4], cy[4], sz[4], cz[4];
-    sincos_multiples(T(x[0]), sx, cx);
-    sincos_multiples(T(x[1]), sy, cy);
-    sincos_multiples(T(x[2]), sz, cz);
     T vx = 0, vy = 0, vz = 0;
     T j00 = 0, j01 = 0, j02 = 0, j10 = 0, j11 = 0, j12 = 0, j20 = 0, j21 = 0, j22 = 0;
     for (int k = 0; k < p.nvp; k++) {
@@ -164,6 +192,55 @@ __device__ __forceinline__ void vel_vecpot(const Vel<T> &p, const double *x, T c
     J[0] = c * j00; J[1] = c * j01; J[2] = c * j02;
     J[3] = c * j10; J[4] = c * j11; J[5] = c * j12;
     J[6] = c * j20; J[7] = c * j21; J[8] = c * j22;
+}
+
+// The same sums with the multiples staged in LDS, value-major (row r of
+// kBlock entries: 0-3 sin(l pi x), 4-7 cos(l pi x), then y, then z), read at
+// each mode's uniform wavenumber rows: a wave-uniform row offset instead of a
+// per-lane select of one of four registers.
+template <typename T>
+__device__ __forceinline__ void vecpot_modes_lds(const Vel<T> &p, const T (*tab)[kBlock],
+                                                 int tid, T c, T *v, T *J)
+{
+    T vx = 0, vy = 0, vz = 0;
+    T j00 = 0, j01 = 0, j02 = 0, j10 = 0, j11 = 0, j12 = 0, j20 = 0, j21 = 0, j22 = 0;
+#pragma unroll 2
+    for (int k = 0; k < p.nvp; k++) {
+        const int l = p.vpi[k][0] - 1, m = p.vpi[k][1] - 1, n = p.vpi[k][2] - 1;
+        const T Sx = tab[l][tid], Cx = tab[4 + l][tid];
+        const T Sy = tab[8 + m][tid], Cy = tab[12 + m][tid];
+        const T Sz = tab[16 + n][tid], Cz = tab[20 + n][tid];
+        const T ss = Sy * Sz, cs = Cy * Sz, sc = Sy * Cz, cc = Cy * Cz;
+        const T SSS = Sx * ss, SCS = Sx * cs, SSC = Sx * sc, SCC = Sx * cc;
+        const T CSS = Cx * ss, CCS = Cx * cs, CSC = Cx * sc;
+        const T *q = p.vpc[k];
+        vx += q[0] * SCS - q[1] * SSC;
+        vy += q[2] * SSC - q[3] * CSS;
+        vz += q[4] * CSS - q[5] * SCS;
+        j00 += q[6] * CCS - q[7] * CSC;
+        j01 -= q[8] * SSS + q[9] * SCC;
+        j02 += q[10] * SCC + q[11] * SSS;
+        j10 += q[12] * CSC + q[13] * SSS;
+        j11 += q[14] * SCC - q[6] * CCS;
+        j12 -= q[15] * SSS + q[16] * CSC;
+        j20 -= q[17] * SSS + q[18] * CCS;
+        j21 += q[19] * CCS + q[20] * SSS;
+        j22 += q[7] * CSC - q[14] * SCC;
+    }
+    v[0] = c * vx; v[1] = c * vy; v[2] = c * vz;
+    J[0] = c * j00; J[1] = c * j01; J[2] = c * j02;
+    J[3] = c * j10; J[4] = c * j11; J[5] = c * j12;
+    J[6] = c * j20; J[7] = c * j21; J[8] = c * j22;
+}
+
+template <typename T>
+__device__ __forceinline__ void vel_vecpot(const Vel<T> &p, const double *x, T c, T *v, T *J)
+{
+    T sx[4], cx[4], sy[4], cy[4], sz[4], cz[4];
+    sincos_multiples(T(x[0]), sx, cx);
+    sincos_multiples(T(x[1]), sy, cy);
+    sincos_multiples(T(x[2]), sz, cz);
+    vecpot_modes(p, sx, cx, sy, cy, sz, cz, c, v, J);
 }
 
 // Divergence-free reading of the 3D deformation field of sec. 6.2:
