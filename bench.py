@@ -685,6 +685,9 @@ def bench_probe(args):
     table = {}
     cases = [("2d", (8192, 8192), 32, BYTES_PER_NODE, PROBE_FLOPS_PER_NODE_2D),
              ("3d", (384, 384, 384), 16, BYTES_PER_NODE_3D, PROBE_FLOPS_PER_NODE_3D)]
+    if args.profile:  # the 2D case for a few steps, then a plain copy
+        cases = [(name, ncell, args.inner or 4, bpn, fpn)
+                 for name, ncell, _, bpn, fpn in cases[:1]]
     for name, ncell, steps, bpn, fpn in cases:
         dim = len(ncell)
         A = np.zeros((dim, dim))
@@ -698,7 +701,7 @@ def bench_probe(args):
         st[1:].normal_()
         g.advance(st, 0.0, dt, 2)  # warm-up
         times = []
-        for _ in range(max(args.steps, 1)):
+        for _ in range(1 if args.profile else max(args.steps, 1)):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
             g.advance(st, 0.0, dt, steps)
@@ -719,6 +722,12 @@ def bench_probe(args):
             f"{tflops:.1f} TFLOP/s ({tflops / VALU_F32_PEAK_TFLOPS:.2f} of VALU)")
         del g, st
         torch.cuda.empty_cache()
+    if args.profile:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        torch.empty_like(src).copy_(src)  # plain copy: reads and writes exactly 256 MiB
+        torch.cuda.synchronize()
+        return 0
     main = table["2d"]
     line = {
         "metric": "bandwidth probe (not a workload): rigid rotation, FP32, 2D 8192^2 and "
@@ -731,7 +740,9 @@ def bench_probe(args):
         "probe": table,
         "roofline": {"bound": "hbm", "achieved": main["hbm_gbps_algorithmic"],
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": main["hbm_frac"],
-                     "traffic": None, "kernel": "k_step2d<float, AFFINE, CENTRAL>"},
+                     "traffic": traffic_record("k_step2d_affine_probe_8192.md",
+                                               SINGLE_KERNEL_SOURCES),
+                     "kernel": "k_step2d<float, AFFINE, CENTRAL>"},
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
@@ -825,7 +836,9 @@ def bench_3d(args):
         "fp32_l1_shape_error": n32[2], "fp32_linf_band_error": n32[3],
         "eval_points_ms": eval_ms,
         "roofline": {"bound": "alu", "achieved": tflops, "peak": VALU_F32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": tflops / VALU_F32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": tflops / VALU_F32_PEAK_TFLOPS,
+                     "traffic": traffic_record("k_step3d_vecpot_f32_256.md",
+                                               SINGLE_KERNEL_SOURCES),
                      "kernel": "k_step3d_vecpot<float, CENTRAL, shift, superconsistent>",
                      "flops_per_launch": nodes * FLOPS_PER_NODE_3D, "avg_launch_us": kernel_us,
                      "hbm_gbps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS},

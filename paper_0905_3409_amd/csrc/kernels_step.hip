@@ -19,7 +19,9 @@ __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st
                                                    const T *__restrict__ grad,
                                                    T *__restrict__ phi_o, T *__restrict__ grad_o)
 {
-    const unsigned id = blockIdx.x * kBlock + threadIdx.x;
+    unsigned blk;
+    if (!xcd_block(unsigned((g.nodes + kBlock - 1) / kBlock), blk)) return;
+    const unsigned id = blk * kBlock + threadIdx.x;
     if (id >= unsigned(g.nodes)) return;
     const unsigned nx = unsigned(g.n[0]);
     const int j = int(id / nx);
@@ -113,7 +115,9 @@ __global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st
                                                    const T *__restrict__ grad,
                                                    T *__restrict__ phi_o, T *__restrict__ grad_o)
 {
-    const unsigned id = blockIdx.x * kBlock + threadIdx.x;
+    unsigned blk;
+    if (!xcd_block(unsigned((g.nodes + kBlock - 1) / kBlock), blk)) return;
+    const unsigned id = blk * kBlock + threadIdx.x;
     if (id >= unsigned(g.nodes)) return;
     const unsigned nx = unsigned(g.n[0]), ny = unsigned(g.n[1]);
     const unsigned row = id / nx;
@@ -217,7 +221,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 {
     constexpr bool LDS = sizeof(T) == 4;
     __shared__ T tab_s[LDS ? 24 : 1][kBlock];
-    const unsigned id = blockIdx.x * kBlock + threadIdx.x;
+    unsigned blk;
+    if (!xcd_block(unsigned((g.nodes + kBlock - 1) / kBlock), blk)) return;
+    const unsigned id = blk * kBlock + threadIdx.x;
     if (id >= unsigned(g.nodes)) return;
     const unsigned nx = unsigned(g.n[0]), ny = unsigned(g.n[1]);
     const unsigned row = id / nx;
@@ -343,7 +349,7 @@ static hipError_t launch_vecpot(const gals_ctx *ctx, const Vel<T> &p, const void
                                 double c1, double c2, double c3, const void *tab, hipStream_t s)
 {
     const Stage<T> st{T(c1), T(c2), T(c3)};
-    const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock);
+    const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock + 7) / 8u * 8u;
     hipLaunchKernelGGL((k_step3d_vecpot<T, MIX, sizeof(T) == 4, PSI>), dim3(blocks),
                        dim3(kBlock), 0, s, ctx->g, p, st, dt, (const T *)tab, (const T *)phi,
                        (const T *)grad, (T *)phi_o, (T *)grad_o);
@@ -356,7 +362,8 @@ static hipError_t launch_typed(const gals_ctx *ctx, const Vel<T> &p, const void 
                                double c2, double c3, hipStream_t s)
 {
     const Stage<T> st{T(c1), T(c2), T(c3)};
-    const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock);
+    // rounded up to a multiple of 8 for the XCD band mapping (xcd_block)
+    const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock + 7) / 8u * 8u;
     if (ctx->dim == 2) {
         if constexpr (KIND == GALS_VEL_AFFINE || KIND == GALS_VEL_STREAM_SIN ||
                       KIND == GALS_VEL_VORTEX || KIND == GALS_VEL_PSEUDO1D) {

@@ -249,4 +249,14 @@ __device__ __forceinline__ bool xcd_tile(unsigned tiles_x, unsigned tiles, unsig
     return t < tiles;
 }
 
+// The same for kernels over a flat node range in blocks of kBlock nodes:
+// XCD x walks a contiguous band of blocks. The grid is rounded up to a
+// multiple of 8; returns false for ids past the last block.
+__device__ __forceinline__ bool xcd_block(unsigned blocks, unsigned &b)
+{
+    const unsigned per = (blocks + 7u) / 8u;
+    b = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+    return b < blocks;
+}
+
 }  // namespace gals
