@@ -4,7 +4,9 @@ benchmark times (one 256-thread block per 256 nodes, one launch per step):
 * 2048^2 stream-function workload, FP64 and FP32: two whole steps against the
   oracle at every node, and single steps from later times at sampled nodes
   (the oracle computes them one by one from the same analytic input).
-* 256^3 vector-potential workload: one step at sampled nodes.
+* 2048^2 FP64: 64 consecutive steps at every node.
+* 256^3 vector-potential workload: one step at sampled nodes, and 16 FP64
+  steps at every node.
 * Whole-run properties that hold at any size: after the full 1024-step
   time-reversed run the FP32 and FP64 GPU states agree closely and return to
   the initial level set.
@@ -62,6 +64,21 @@ def test_c2_fp32_two_steps_every_node(c2, c2_oracle_two_steps):
     assert ep <= tp and eg <= tg
 
 
+def test_c2_fp64_64_steps_every_node(c2):
+    """64 consecutive FP64 steps of the 2048^2 workload against the oracle at
+    every node (the oracle takes about 15 s on 16 host threads)."""
+    w = c2
+    print("C2 fp64 64 steps: oracle ...", flush=True)
+    o = oracle.advance(2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
+                       w["phi0"], w["psi0"], 0.0, w["dt"], 64)
+    g, st = _gpu(w, "float64", 0.0, 64)
+    phi, psi = g.to_numpy(st)
+    print(f"C2 fp64 64 steps: phi {rel(phi, o[0]):.2e} "
+          f"psi/scale {rel_psi(psi, o[1], o[0], 1 / 2048):.2e}", flush=True)
+    assert rel(phi, o[0]) <= TOL64
+    assert rel_psi(psi, o[1], o[0], 1 / 2048) <= TOL64
+
+
 @pytest.mark.parametrize("t0", [0.5, 1.0, 1.75])
 def test_c2_fp64_sampled_steps_at_later_times(c2, t0):
     w = c2
@@ -104,6 +121,26 @@ def test_c3_one_step_sampled(c3, dtype):
         tp, tg = fp32_tolerances(w["phi0"], w["psi0"], 1 / 256, 1)
         print(f"C3 fp32 1 step sampled: phi {ep:.2e} (tol {tp:.1e}) psi {eg:.2e} (tol {tg:.1e})")
         assert ep <= tp and eg <= tg
+
+
+def test_c3_fp64_16_steps_every_node(c3):
+    """16 consecutive FP64 steps of the 256^3 vector-potential workload
+    against the oracle at every node (the oracle's 3D step is the costly
+    part: about 6 s a step on 16 host threads)."""
+    import time
+    w = c3
+    a = time.perf_counter()
+    o = oracle.advance(3, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
+                       w["phi0"], w["psi0"], 0.0, w["dt"], 16)
+    print(f"C3 fp64 16 steps: oracle {time.perf_counter() - a:.0f} s", flush=True)
+    g, st = _gpu(w, "float64", 0.0, 16)
+    phi, psi = g.to_numpy(st)
+    del st
+    hmin = 1 / 256
+    print(f"C3 fp64 16 steps: phi {rel(phi, o[0]):.2e} "
+          f"psi/scale {rel_psi(psi, o[1], o[0], hmin):.2e}", flush=True)
+    assert rel(phi, o[0]) <= TOL64
+    assert rel_psi(psi, o[1], o[0], hmin) <= TOL64
 
 
 def test_c2_full_run_fp32_tracks_fp64_and_returns(c2):
