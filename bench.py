@@ -273,6 +273,17 @@ def main():
                "sample": f"first {k_cpu} of the {w['steps']} steps of the same 2048^2 workload "
                          f"(FP64 oracle, OpenMP), {b - a:.1f} s"}
         log(f"cpu oracle: {cpu['value'] / 1e6:.2f} M node-upd/s on {cpu['cores']} threads")
+        # and on one core: the first step
+        threads = oracle.num_threads()
+        oracle.set_threads(1)
+        a = time.perf_counter()
+        oracle.advance(2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
+                       w["phi0"], w["psi0"], 0.0, w["dt"], 1)
+        b = time.perf_counter()
+        oracle.set_threads(threads)
+        cpu["single_core"] = {"value": nodes / (b - a), "unit": "node-updates/s", "cores": 1,
+                              "sample": f"the first step, {b - a:.1f} s"}
+        log(f"cpu oracle, 1 core: {nodes / (b - a) / 1e6:.3f} M node-upd/s")
 
     line = {
         "metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
@@ -389,6 +400,17 @@ def bench_batched(args):
                          f"({len(sample)} grids, {snodes} nodes; FP64 oracle, OpenMP), "
                          f"{c - a:.1f} s"}
         log(f"cpu oracle: {cpu['value'] / 1e6:.2f} M node-upd/s on {cpu['cores']} threads")
+        # and on one core: the first step
+        threads = oracle.num_threads()
+        oracle.set_threads(1)
+        a = time.perf_counter()
+        oracle.advance(2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
+                       w["phi0"], w["psi0"], 0.0, w["dt"], 1)
+        b = time.perf_counter()
+        oracle.set_threads(threads)
+        cpu["single_core"] = {"value": nodes / (b - a), "unit": "node-updates/s", "cores": 1,
+                              "sample": f"the first step, {b - a:.1f} s"}
+        log(f"cpu oracle, 1 core: {nodes / (b - a) / 1e6:.3f} M node-upd/s")
     line = {
         "metric": "GALS batched node-updates/s (512 uneven 2D grids, one launch per step)",
         "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps,

@@ -63,6 +63,7 @@ def _load():
     lib.orc_apply_inflow.argtypes = [i, L, D, D, i, D, l, d, d, d, D, D, D, D, D]
     lib.orc_grad_cs.argtypes = [L, D, D, D, l, d, i, i, D, D, d, d, l, D, D, d, D, D]
     lib.orc_num_threads.argtypes = []
+    lib.orc_set_threads.argtypes = [i]
     _lib = lib
     return lib
 
@@ -93,6 +94,11 @@ def _check(rc, what):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    _check(_load().orc_set_threads(int(n)), "set_threads")
 
 
 def basis(v: int, alpha: int, deriv: int, x: float) -> float:

@@ -1021,6 +1021,16 @@ double orc_max_speed(int dim, const long *ncell, const double *lo, const double 
     return best;
 }
 
+/* Threads of the OpenMP loops from now on (n >= 1). */
+int orc_set_threads(int n)
+{
+    if (n < 1) return -1;
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#endif
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

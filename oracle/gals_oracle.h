@@ -141,6 +141,8 @@ int orc_grad_cs(const long *ncell, const double *lo, const double *hi, const dou
                 const double *phi_target, double eps, double *value, double *grad);
 
 /* Number of OpenMP threads the oracle runs with (1 without OpenMP). */
+/* Threads of the OpenMP loops from now on (n >= 1). */
+int orc_set_threads(int n);
 int orc_num_threads(void);
 
 #ifdef __cplusplus

@@ -1244,3 +1244,19 @@ def test_face_scheme_reduces_to_the_2d_step(mixed):
     assert rel_err(ps3[1, face], ps2[0]) <= 1e-13
     assert rel_err(ps3[2, face], ps2[1]) <= 1e-13
     assert np.all(ps3[0, face] == 0.0)
+
+
+def test_oracle_result_does_not_depend_on_its_thread_count():
+    """Each node's update reads only the old state, so the OpenMP split of
+    the node loop cannot change a bit of the result."""
+    w = inputs.rotation_circle(seed=3)
+    args = (2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"], w["phi0"],
+            w["psi0"], 0.0, w["dt"], 5)
+    many = oracle.advance(*args)
+    threads = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        one = oracle.advance(*args)
+    finally:
+        oracle.set_threads(threads)
+    assert np.array_equal(many[0], one[0]) and np.array_equal(many[1], one[1])
