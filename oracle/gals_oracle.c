@@ -589,8 +589,9 @@ static int step_node(const grid_t *g, int kind, const double *params, long np,
         /* homogeneous Neumann: project the foot onto the domain */
         for (int a = 0; a < d; a++) {
             double top = g->lo[a] + (double)g->nc[a] * g->h[a];
-            if (X[a] < g->lo[a]) { X[a] = g->lo[a]; outside[a] = 1; }
-            else if (X[a] > top) { X[a] = top; outside[a] = 1; }
+            double tol = ORC_FOOT_TOL * g->h[a];
+            if (X[a] < g->lo[a] - tol) { X[a] = g->lo[a]; outside[a] = 1; }
+            else if (X[a] > top + tol) { X[a] = top; outside[a] = 1; }
         }
     }
     locate(g, X, cell, xi);
@@ -721,8 +722,9 @@ static int face_node(const grid_t *g, int kind, const double *params, long np, d
     for (int i = 0; i < k; i++) {
         int a = tax[i];
         double top = g->lo[a] + (double)g->nc[a] * g->h[a];
-        if (X[a] < g->lo[a]) { X[a] = g->lo[a]; outside[i] = 1; }
-        else if (X[a] > top) { X[a] = top; outside[i] = 1; }
+        double tol = ORC_FOOT_TOL * g->h[a];
+        if (X[a] < g->lo[a] - tol) { X[a] = g->lo[a]; outside[i] = 1; }
+        else if (X[a] > top + tol) { X[a] = top; outside[i] = 1; }
     }
     locate(g, X, fullcell, xi_full);
     for (int i = 0; i < k; i++) {

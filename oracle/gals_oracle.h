@@ -43,6 +43,13 @@
 #ifndef GALS_ORACLE_H
 #define GALS_ORACLE_H
 
+/* A foot counts as outside the domain (bc 0 and 3) only when it lies more
+ * than ORC_FOOT_TOL cells beyond the boundary; closer, it stays where it is
+ * and the boundary cell's cubic is evaluated there. A foot within rounding
+ * of the boundary (a node on a face the flow runs along) must not have its
+ * normal derivative zeroed or kept by the sign of that rounding. */
+#define ORC_FOOT_TOL 1e-6
+
 #ifdef __cplusplus
 extern "C" {
 #endif

@@ -212,8 +212,9 @@ static void step_cs(const grid2_t *g, const double *params, long nmodes, int pm,
         if (bc == 0) { /* homogeneous Neumann: project the foot onto the domain */
             for (int a = 0; a < 2; a++) {
                 double top = g->lo[a] + (double)g->nc[a] * g->h[a];
-                if (creal(X[a]) < g->lo[a]) { X[a] = g->lo[a]; outside[a] = 1; }
-                else if (creal(X[a]) > top) { X[a] = top; outside[a] = 1; }
+                double tol = ORC_FOOT_TOL * g->h[a];
+                if (creal(X[a]) < g->lo[a] - tol) { X[a] = g->lo[a]; outside[a] = 1; }
+                else if (creal(X[a]) > top + tol) { X[a] = top; outside[a] = 1; }
             }
         }
         for (int a = 0; a < 2; a++) { /* cell from the real part, xi keeps the imaginary part */

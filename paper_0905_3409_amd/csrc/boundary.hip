@@ -189,10 +189,11 @@ __device__ __forceinline__ void face_update(const Geom &g, const Vel<T> &p, cons
     for (int i = 0; i < K; i++) {
         const int a = tax[i];
         double Xa = X[a];
-        if (Xa < g.lo[a]) {
+        const double tol = kFootTol * g.h[a];  // as project_foot
+        if (Xa < g.lo[a] - tol) {
             Xa = g.lo[a];
             out |= 1u << i;
-        } else if (Xa > g.top[a]) {
+        } else if (Xa > g.top[a] + tol) {
             Xa = g.top[a];
             out |= 1u << i;
         }

@@ -107,8 +107,14 @@ __device__ __forceinline__ void heun_gradient(const T *Af, const T *An, T dtT, c
 
 // ---------------------------------------------------------------------------
 // Homogeneous Neumann treatment of a foot outside the domain: project it onto
-// the domain and remember the axes whose normal derivative must vanish.
+// the domain and remember the axes whose normal derivative must vanish. A
+// foot counts as outside only when it lies more than kFootTol cells beyond
+// the boundary; closer, it stays where it is (the boundary cell's cubic is
+// evaluated there), so that a foot within rounding of the boundary, e.g. of a
+// node on a face the flow runs along, is not decided by that rounding.
 // ---------------------------------------------------------------------------
+constexpr double kFootTol = 1e-6;
+
 template <int D>
 __device__ __forceinline__ unsigned project_foot(const Geom &g, double *X)
 {
@@ -116,10 +122,11 @@ __device__ __forceinline__ unsigned project_foot(const Geom &g, double *X)
     if (g.bc == GALS_BC_NEUMANN) {
 #pragma unroll
         for (int a = 0; a < D; a++) {
-            if (X[a] < g.lo[a]) {
+            const double tol = kFootTol * g.h[a];
+            if (X[a] < g.lo[a] - tol) {
                 X[a] = g.lo[a];
                 out |= 1u << a;
-            } else if (X[a] > g.top[a]) {
+            } else if (X[a] > g.top[a] + tol) {
                 X[a] = g.top[a];
                 out |= 1u << a;
             }

@@ -184,8 +184,9 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
 #pragma unroll
     for (int a = 0; a < 2; a++) {
         if (g.bc == GALS_BC_NEUMANN) {
-            if (s[a] < 0.0) { s[a] = 0.0; f.out |= 1u << a; }
-            else if (s[a] > double(g.nc[a])) { s[a] = double(g.nc[a]); f.out |= 1u << a; }
+            // outside only beyond kFootTol cells (project_foot)
+            if (s[a] < -kFootTol) { s[a] = 0.0; f.out |= 1u << a; }
+            else if (s[a] > double(g.nc[a]) + kFootTol) { s[a] = double(g.nc[a]); f.out |= 1u << a; }
         }
         // cell index clamped to [0, nc-1], local coordinate unclamped
         const double fl = fmin(fmax(floor(s[a]), 0.0), double(g.nc[a] - 1));

@@ -391,3 +391,53 @@ def test_face_scheme_large_grid_sampled(dtype):
     # some boundary nodes took the face scheme: psi normal component exactly 0
     # where the oracle says so
     assert np.sum(go[: bnd.size] == 0.0) > 100
+
+
+@pytest.mark.parametrize("bc", [pkg.BC_INFLOW, pkg.BC_INFLOW_NEUMANN])
+def test_fp32_3d_boundary_conditions(bc):
+    """FP32 3D vector-potential kernel (tables, shifted stages) followed by
+    either boundary kernel, against the FP64 oracle."""
+    from gpu_util import gpu_advance
+    name, dim, kind, params, period, ncell, lo, hi, dt, steps = CASES[4]
+    coords = _coords(ncell, lo, hi)
+    base = _moving_data(coords, k=[2.1, 1.3, 1.7], w=1.9)
+    data = _nearly_consistent(base, coords, ncell, kind, params, period)
+    phi0, psi0, _ = data(0.05)
+    args = (dim, ncell, lo, hi, kind, params, period, phi0, psi0, 0.05, dt, steps)
+    if bc == pkg.BC_INFLOW:
+        g = gpu_inflow(*args, data, dtype="float32")
+        o = oracle.advance_inflow(*args, data)
+    else:
+        g = gpu_advance(*args, dtype="float32", bc=bc)
+        o = oracle.advance(*args, bc=oracle.BC_INFLOW_NEUMANN)
+    hmin = min((hi[a] - lo[a]) / ncell[a] for a in range(dim))
+    tp, tg = fp32_tolerances(o[0], o[1], hmin, steps)
+    print(f"3D fp32 bc={bc}: phi {rel(g[0], o[0]):.2e} (tol {tp:.1e}) psi {rel(g[1], o[1]):.2e} "
+          f"(tol {tg:.1e})")
+    assert rel(g[0], o[0]) <= tp
+    assert rel(g[1], o[1]) <= tg
+
+
+@pytest.mark.parametrize("ncell", [(2, 2), (2, 3), (2, 2, 2), (3, 2, 2)])
+@pytest.mark.parametrize("bc", [pkg.BC_INFLOW, pkg.BC_INFLOW_NEUMANN])
+def test_boundary_conditions_on_minimal_grids(ncell, bc):
+    """Every node is a boundary node and most lie on several faces: the
+    boundary enumeration must visit each once."""
+    from gpu_util import gpu_advance
+    dim = len(ncell)
+    lo, hi = (-0.1,) * dim, (1.05,) * dim
+    params = _rotation(dim)
+    coords = _coords(ncell, lo, hi)
+    base = _moving_data(coords, k=[2.1, 1.3, 1.7][:dim], w=1.9)
+    data = _nearly_consistent(base, coords, ncell, inputs.AFFINE, params, 0.0)
+    phi0, psi0, _ = data(0.0)
+    args = (dim, ncell, lo, hi, inputs.AFFINE, params, 0.0, phi0, psi0, 0.0, 0.05, 3)
+    if bc == pkg.BC_INFLOW:
+        g = gpu_inflow(*args, data)
+        o = oracle.advance_inflow(*args, data)
+    else:
+        g = gpu_advance(*args, dtype="float64", bc=bc)
+        o = oracle.advance(*args, bc=oracle.BC_INFLOW_NEUMANN)
+    hmin = min((hi[a] - lo[a]) / ncell[a] for a in range(dim))
+    assert rel(g[0], o[0]) <= TOL64
+    assert rel_psi(g[1], o[1], o[0], hmin) <= TOL64

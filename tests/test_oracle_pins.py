@@ -1260,3 +1260,29 @@ def test_oracle_result_does_not_depend_on_its_thread_count():
     finally:
         oracle.set_threads(threads)
     assert np.array_equal(many[0], one[0]) and np.array_equal(many[1], one[1])
+
+
+@pytest.mark.parametrize("cells_out", [1e-9, 1e-4])
+def test_feet_within_the_margin_keep_their_gradient(cells_out):
+    """A foot less than 1e-6 cells beyond the boundary stays where it is and
+    keeps the interpolant's gradient (translation of a cubic stays exact);
+    one 1e-4 cells out is projected and its normal derivative zeroed."""
+    rng = np.random.default_rng(220)
+    n, dt = 10, 0.05
+    ncell = (n, n)
+    coords = inputs.node_grid(ncell)
+    p = Poly.random_total_degree(rng, 2, 3)
+    phi, psi = poly_state(p, coords)
+    b = np.array([-cells_out * (1.0 / n) / dt, 0.3])  # x-feet of the x = 1 face just outside
+    params = inputs.affine_params(b, np.zeros(2), np.zeros((2, 2)))
+    ph, ps = oracle.advance(2, ncell, [0, 0], [1, 1], inputs.AFFINE, params, 0.0, phi, psi, 0.0,
+                            dt, 1)
+    face = (coords[0] == 1.0) & (coords[1] >= 0.3 * dt)  # y-feet inside
+    foot = [coords[0] - b[0] * dt, coords[1] - b[1] * dt]
+    want_psi_x = p.deriv((1, 0))(*foot)
+    ps = ps.reshape(2, -1)
+    if cells_out < 1e-6:
+        assert np.max(np.abs(ps[0, face] - want_psi_x[face])) <= 1e-11
+        assert np.max(np.abs(ph[face] - p(*foot)[face])) <= 1e-12
+    else:
+        assert np.all(ps[0, face] == 0.0)
