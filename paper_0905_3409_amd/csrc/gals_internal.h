@@ -14,7 +14,8 @@ constexpr int kMaxStreamModes = 64;  // user modes of GALS_VEL_STREAM_SIN
 constexpr int kMaxVecpotModes = 8;   // user modes of GALS_VEL_VECPOT_SIN
 constexpr int kRedBlocks = 1024;     // partial sums of the deterministic reductions
 constexpr int kRedSlots = 8;         // doubles per partial
-constexpr int kJet = 20;             // stream-function table entries per column / row
+constexpr int kJetTaylor = 20;       // stream-function jet entries per column / row
+constexpr int kJet = 24;             // table stride: the jet, sin and cos of pi x, 2 unused
 // Taylor evaluation of the FP32 stream-function velocity at a stage point is
 // used while kx |dx| + ky |dy| stays below this bound (truncation < FP32 rounding)
 constexpr float kTaylorMax = 0.03f;

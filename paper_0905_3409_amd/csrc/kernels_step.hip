@@ -137,9 +137,10 @@ __global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st
 // Sine vector potentials in 3D: sin(pi x) and cos(pi x) of every node
 // coordinate come from per-axis tables (FP64-built, one pair per node along
 // each axis); the three stages take the multiples of the node's angles, and
-// in FP32 (SHIFT) the two off-node stages shift them by angle addition
-// whenever every offset is below kShiftMax / pi, instead of evaluating sin
-// and cos at the stage points. The mode sums are those of vel_vecpot.
+// (SHIFT) the two off-node stages shift them by angle addition whenever
+// every offset is small enough for the series of the precision, instead of
+// evaluating sin and cos at the stage points. The mode sums are those of
+// vel_vecpot.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_axis_tables(Geom g, T *__restrict__ tab)
@@ -184,17 +185,24 @@ __device__ __forceinline__ void stage_vecpot(const Vel<T> &p, T (*tab)[kBlock], 
                                              T cf, T *v, T *A)
 {
     T sx[4], cx[4], sy[4], cy[4], sz[4], cz[4];
+    // FP32: the short series up to |pi d| = kShiftMax; FP64: the long one
+    constexpr double kMax = sizeof(T) == 4 ? kShiftMax : kShiftMaxLong<T>;
     bool near = SHIFT;
     T d[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         d[a] = T(xs[a] - x[a]);
-        near = near && fabs(d[a]) <= T(kShiftMax / kPi);
+        near = near && fabs(d[a]) <= T(kMax / kPi);
     }
     if (near) {
         T s[3], c[3];
 #pragma unroll
-        for (int a = 0; a < 3; a++) shifted_sincos(s1[a], c1[a], d[a], s[a], c[a]);
+        for (int a = 0; a < 3; a++) {
+            if constexpr (sizeof(T) == 4)
+                shifted_sincos(s1[a], c1[a], d[a], s[a], c[a]);
+            else
+                shifted_sincos_long(s1[a], c1[a], d[a], s[a], c[a]);
+        }
         multiples_from(s[0], c[0], sx, cx);
         multiples_from(s[1], c[1], sy, cy);
         multiples_from(s[2], c[2], sz, cz);
@@ -350,7 +358,7 @@ static hipError_t launch_vecpot(const gals_ctx *ctx, const Vel<T> &p, const void
 {
     const Stage<T> st{T(c1), T(c2), T(c3)};
     const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock + 7) / 8u * 8u;
-    hipLaunchKernelGGL((k_step3d_vecpot<T, MIX, sizeof(T) == 4, PSI>), dim3(blocks),
+    hipLaunchKernelGGL((k_step3d_vecpot<T, MIX, true, PSI>), dim3(blocks),
                        dim3(kBlock), 0, s, ctx->g, p, st, dt, (const T *)tab, (const T *)phi,
                        (const T *)grad, (T *)phi_o, (T *)grad_o);
     return hipGetLastError();

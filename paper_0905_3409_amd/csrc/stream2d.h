@@ -13,7 +13,9 @@ namespace gals {
 //   coltab[i][a][n] = sum_m S[m][n] (m pi)^a sin^(a)(m pi x_i)
 //   rowtab[j][b][n] = (n pi)^b sin^(b)(n pi y_j)
 //   d^a/dx^a d^b/dy^b s(x_i, y_j) = sum_n coltab[i][a][n] rowtab[j][b][n]
-// with sin^(a) = sin, cos, -sin, -cos, sin for a = 0..4. Entries are built in
+// with sin^(a) = sin, cos, -sin, -cos, sin for a = 0..4; entries kJetTaylor
+// and kJetTaylor + 1 hold sin(pi x_i), cos(pi x_i) (sin(pi y_j), cos(pi y_j)
+// in a row), for the stages evaluated by the modal sum. Entries are built in
 // FP64 and rounded to T. id < n[0]: column id; n[0] <= id < n[0]+n[1]: row.
 template <typename T>
 __device__ __forceinline__ void stream_table_entry(const Geom &g, const double (&S)[4][4], int id,
@@ -37,6 +39,10 @@ __device__ __forceinline__ void stream_table_entry(const Geom &g, const double (
                 }
                 coltab[int64_t(id) * kJet + 4 * a + n] = T(u);
             }
+        T *raw = coltab + int64_t(id) * kJet + kJetTaylor;
+        raw[0] = T(s[0]);
+        raw[1] = T(c[0]);
+        raw[2] = raw[3] = T(0);
     } else if (id < nx + ny) {
         const int j = id - nx;
         const double y = node_coord(g.lo[1], j, g.h[1]);
@@ -52,6 +58,12 @@ __device__ __forceinline__ void stream_table_entry(const Geom &g, const double (
                 kb *= k;
             }
         }
+        double s1, c1;
+        sincospi(y, &s1, &c1);
+        T *raw = rowtab + int64_t(j) * kJet + kJetTaylor;
+        raw[0] = T(s1);
+        raw[1] = T(c1);
+        raw[2] = raw[3] = T(0);
     }
 }
 
@@ -113,17 +125,33 @@ __device__ __forceinline__ void stream_taylor(const StreamJet<T> &J, T dx, T dy,
 // polynomial of the node's jet when its truncation stays below FP32 rounding
 // (kx |dx| + ky |dy| <= kTaylorMax), the exact modal sum otherwise (and
 // always in FP64). P carries the stream tables S, SQ, SR and kx, ky.
+// Otherwise the modal sum; in FP64, sin and cos of the stage point's angles
+// come from the node's (entries kJetTaylor.. of its table rows U, Y) by angle
+// addition when the offset allows (FP32 keeps sincospi there: the branch is
+// rare, and the extra registers would cost the batched kernel a spill).
 template <typename T, bool TAYLOR, class P>
-__device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J, double x0,
-                                             double y0, T dx, T dy, T c, T *v, T *A)
+__device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J,
+                                             const T *__restrict__ U, const T *__restrict__ Y,
+                                             double x0, double y0, T dx, T dy, T c, T *v, T *A)
 {
     if (TAYLOR && p.kx * fabs(dx) + p.ky * fabs(dy) <= T(kTaylorMax)) {
         T sx, sy, sxx, sxy, syy;
         stream_taylor(J, dx, dy, sx, sy, sxx, sxy, syy);
         from_stream(sx, sy, sxx, sxy, syy, c, v, A);
     } else {
-        const double pos[2] = {x0 + double(dx), y0 + double(dy)};
-        vel_stream(p, pos, c, v, A);
+        T sx[4], cx[4], sy[4], cy[4];
+        constexpr T dmax = T(kShiftMaxLong<T> / kPi);
+        if (sizeof(T) == 8 && fabs(dx) <= dmax && fabs(dy) <= dmax) {
+            T s, cs;
+            shifted_sincos_long(U[kJetTaylor], U[kJetTaylor + 1], dx, s, cs);
+            multiples_from(s, cs, sx, cx);
+            shifted_sincos_long(Y[kJetTaylor], Y[kJetTaylor + 1], dy, s, cs);
+            multiples_from(s, cs, sy, cy);
+        } else {
+            sincos_multiples(T(x0 + double(dx)), sx, cx);
+            sincos_multiples(T(y0 + double(dy)), sy, cy);
+        }
+        stream_modes(p, sx, cx, sy, cy, c, v, A);
     }
 }
 
@@ -152,9 +180,9 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
 {
     StreamJet<T> &jet = f.jet;
     {
-        T y[kJet], u[kJet];
+        T y[kJetTaylor], u[kJetTaylor];
 #pragma unroll
-        for (int k = 0; k < kJet; k++) {
+        for (int k = 0; k < kJetTaylor; k++) {
             y[k] = Y[k];
             u[k] = U[k];
         }
@@ -167,11 +195,11 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
     // stage 2 at x1 = x - dt v0, time t
     f.d1[0] = -dtT * f.v0[0];
     f.d1[1] = -dtT * f.v0[1];
-    stream_stage<T, TAYLOR>(p, jet, x0, y0, f.d1[0], f.d1[1], st.c2, f.v1, f.A1);
+    stream_stage<T, TAYLOR>(p, jet, U, Y, x0, y0, f.d1[0], f.d1[1], st.c2, f.v1, f.A1);
     // stage 3 at x2 = x - dt (v0 + v1) / 4, time t + dt/2
     f.d2[0] = -dtT * (T(0.25) * f.v0[0] + T(0.25) * f.v1[0]);
     f.d2[1] = -dtT * (T(0.25) * f.v0[1] + T(0.25) * f.v1[1]);
-    stream_stage<T, TAYLOR>(p, jet, x0, y0, f.d2[0], f.d2[1], st.c3, f.v2, f.A2);
+    stream_stage<T, TAYLOR>(p, jet, U, Y, x0, y0, f.d2[0], f.d2[1], st.c3, f.v2, f.A2);
     if constexpr (CHAIN) jacobian_chain<T, 2>(f.A0, f.A1, f.A2, dtT, f.J);
 
     // foot in cell units, FP64: s = node - dt (v0/6 + v1/6 + 2 v2/3) / h
@@ -225,7 +253,7 @@ __device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Sta
         const double x0 = node_coord(g.lo[0], i, g.h[0]), y0 = node_coord(g.lo[1], j, g.h[1]);
         T vf[2], Af[4], ps[2];
         const T gH[2] = {Hx, Hy};
-        stream_stage<T, TAYLOR>(p, f.jet, x0, y0, T((f.s[0] - double(i)) * g.h[0]),
+        stream_stage<T, TAYLOR>(p, f.jet, U, Y, x0, y0, T((f.s[0] - double(i)) * g.h[0]),
                                 T((f.s[1] - double(j)) * g.h[1]), st.c2, vf, Af);
         heun_gradient<T, 2>(Af, f.A0, T(dt), gH, ps);
         gx_o[o] = ps[0];

@@ -218,7 +218,7 @@ def test_batch_layout_and_workspace():
         assert total.value == o
         ws = ctypes.c_size_t()
         assert L.gals_batch_workspace_bytes(b, ctypes.byref(ws)) == pkg.OK
-        tables = sum(nx + ny + 2 for nx, ny in ncells) * 20 * es
+        tables = sum(nx + ny + 2 for nx, ny in ncells) * 24 * es  # 24 entries a column/row
         assert total.value * es + tables <= ws.value <= total.value * es + tables + 256 * (n * 64 + 2)
         L.gals_batch_destroy(b)
 
