@@ -55,6 +55,26 @@ def test_fp64_2d_parity(name, kind, params, period, dt, steps, mixed):
     assert rel_psi(g[1], o[1], o[0], hmin) <= TOL64
 
 
+def test_fp64_stream_both_stage_branches():
+    """FP64 stream-function kernel with offsets |pi d| from about 0 to 0.4:
+    stage angles by angle addition where |pi d| <= 0.1, sincospi beyond;
+    both against the oracle."""
+    rng = np.random.default_rng(31)
+    ncell, lo, hi = (41, 37), (-0.1, 0.05), (1.15, 0.95)
+    phi0, psi0 = _random_smooth_state(rng, ncell, lo, hi)
+    params = np.array([0.5, 1, 2, -0.3, 2, 1, 0.2, 3, 3])
+    v = oracle.max_speed(2, ncell, lo, hi, inputs.STREAM_SIN, params, 0.0, 0.0)
+    dt = 0.4 / (np.pi * v)  # the fastest nodes move 0.4 / pi: beyond the series' range
+    args = (2, ncell, lo, hi, inputs.STREAM_SIN, params, 0.0, phi0, psi0, 0.0, dt, 4)
+    g = gpu_advance(*args, dtype="float64")
+    o = oracle_advance(*args)
+    hmin = min((hi[a] - lo[a]) / ncell[a] for a in range(2))
+    print(f"fp64 stream, max |pi d| 0.4: phi {rel(g[0], o[0]):.2e} "
+          f"psi/scale {rel_psi(g[1], o[1], o[0], hmin):.2e}")
+    assert rel(g[0], o[0]) <= TOL64
+    assert rel_psi(g[1], o[1], o[0], hmin) <= TOL64
+
+
 CASES_3D = [
     ("affine", inputs.AFFINE,
      inputs.affine_params([0.05, 0.0, -0.1], [0.5, 0.5, 0.5],
