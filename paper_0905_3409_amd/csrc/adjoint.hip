@@ -114,6 +114,25 @@ __device__ __forceinline__ void mul2(const T *A, const T *B, T *C)
 
 __device__ __forceinline__ void scatter(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// sin(l pi x'), cos(l pi x') for l = 1..4 at x' = x + d from sin and cos of
+// pi x (the node's table entries): angle addition when the offset is in the
+// series' range (as in the 3D step), sincospi otherwise.
+template <typename T>
+__device__ __forceinline__ void stage_multiples(T s1, T c1, double x, T d, T *s, T *c)
+{
+    constexpr double kMax = sizeof(T) == 4 ? kShiftMax : kShiftMaxLong<T>;
+    if (fabs(d) <= T(kMax / kPi)) {
+        T ss, cc;
+        if constexpr (sizeof(T) == 4)
+            shifted_sincos(s1, c1, d, ss, cc);
+        else
+            shifted_sincos_long(s1, c1, d, ss, cc);
+        multiples_from(ss, cc, s, c);
+    } else {
+        sincos_multiples(T(x + double(d)), s, c);
+    }
+}
+
 // LDS tile of the block's scatter: fields x nodes, nodes per row x rows.
 constexpr int kTileW = 96, kTileH = 12;
 
@@ -281,9 +300,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         T sb[16];
 #pragma unroll
         for (int q = 0; q < 16; q++) sb[q] = T(0);
+        // sin and cos of pi x and pi y at the node (table entries kJetTaylor..)
+        const T *cr = coltab + int64_t(i) * kJet + kJetTaylor;
+        const T *rr = rowtab + int64_t(j) * kJet + kJetTaylor;
         // stage 3 at x2 = x - dt (v0 + v1) / 4: v2 = c3 v(x2), A2 = c3 grad v(x2)
-        sincos_multiples(T(x0 + double(f.d2[0])), sx, cx);
-        sincos_multiples(T(y0 + double(f.d2[1])), sy, cy);
+        stage_multiples(cr[0], cr[1], x0, f.d2[0], sx, cx);
+        stage_multiples(rr[0], rr[1], y0, f.d2[1], sy, cy);
         mode_terms(st.c3, v2b, A2b, sx, cx, sy, cy, sb);
         third_derivs(p, sx, cx, sy, cy, t3);
         {
@@ -298,8 +320,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             }
         }
         // stage 2 at x1 = x - dt v0
-        sincos_multiples(T(x0 + double(f.d1[0])), sx, cx);
-        sincos_multiples(T(y0 + double(f.d1[1])), sy, cy);
+        stage_multiples(cr[0], cr[1], x0, f.d1[0], sx, cx);
+        stage_multiples(rr[0], rr[1], y0, f.d1[1], sy, cy);
         mode_terms(st.c2, v1b, A1b, sx, cx, sy, cy, sb);
         third_derivs(p, sx, cx, sy, cy, t3);
         {
@@ -311,8 +333,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             for (int a = 0; a < 2; a++) v0b[a] += -dtT * x1b[a];
         }
         // stage 1 at the node
-        sincos_multiples(T(x0), sx, cx);
-        sincos_multiples(T(y0), sy, cy);
+        multiples_from(cr[0], cr[1], sx, cx);
+        multiples_from(rr[0], rr[1], sy, cy);
         mode_terms(st.c1, v0b, A0b, sx, cx, sy, cy, sb);
 #pragma unroll
         for (int q = 0; q < 16; q++) gacc[q] += double(sb[q]);
