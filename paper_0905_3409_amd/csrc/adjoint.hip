@@ -207,8 +207,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(grad, g.plane),
                          plane_rsrc(grad + g.plane, g.plane), f.cell[0], f.cell[1], d);
         Basis<T> bx, by;
-        basis<T, true>(T(f.xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
-        basis<T, true>(T(f.xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
+        basis<T, true>(T(f.xi[0]), geo_h<T>(g, 0), geo_ih<T>(g, 0), bx);
+        basis<T, true>(T(f.xi[1]), geo_h<T>(g, 1), geo_ih<T>(g, 1), by);
         T H, Gr[2], Hs[4];
         hermite2d_full(d, bx, by, H, Gr, Hs);
 
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             // transpose of approach (B): phi_xy[v] = 3/4 (ea[vx] + eb[vy])
             // - 1/4 (ea[1-vx] + eb[1-vy]) with ea[k] = (psi_x[k+2] - psi_x[k]) / hy
             // and eb[k] = (psi_y[2k+1] - psi_y[2k]) / hx, all within the cell
-            const double ihx = double(T(g.inv_h[0])), ihy = double(T(g.inv_h[1]));
+            const double ihx = double(geo_ih<T>(g, 0)), ihy = double(geo_ih<T>(g, 1));
             double ea[2] = {0.0, 0.0}, eb[2] = {0.0, 0.0};
 #pragma unroll
             for (int v = 0; v < 4; v++) {
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     const bool any = s_box[0] <= s_box[1] && s_box[2] <= s_box[3];
     const int bx0 = s_box[0] - 1, by0 = s_box[2];
     const int bw = any ? s_box[1] - s_box[0] + 4 : 0, bh = any ? s_box[3] - s_box[2] + 2 : 0;
-    const double inv2h = double(T(0.5 * g.inv_h[0]));
+    const double inv2h = double(geo_i2h<T>(g, 0));
     if (any && bw <= kTileW && bh <= kTileH) {
         const int area = bw * bh;
         for (int e = threadIdx.x; e < 3 * area; e += kBlock) s_tile[e] = 0.0;
@@ -457,7 +457,7 @@ static void launch_adj(const gals_ctx *ctx, const Vel<T> &p, const void *phi, co
                        double c1, double c2, double c3, const void *coltab, const void *rowtab,
                        hipStream_t s)
 {
-    const Stage<T> st{T(c1), T(c2), T(c3)};
+    const Stage<T> st = make_stage<T>(dt, c1, c2, c3);
     if (clear)
         hipLaunchKernelGGL((k_adjoint2d_stream<T, MIX, sizeof(T) == 4, true>),
                            dim3(adjoint_blocks(ctx)), dim3(kBlock), 0, s, ctx->g, p, st, dt,

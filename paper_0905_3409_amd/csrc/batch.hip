@@ -68,8 +68,7 @@ __device__ __forceinline__ void batch_tile(const BatchProb<T> &P, unsigned local
     const T *phi = in + P.off;
     T *po = out + P.off;
     stream_node<T, MIX, TAYLOR>(g, P, st, dt, col + int64_t(i) * kJet, row + int64_t(j) * kJet,
-                                plane_rsrc(phi, g.plane), plane_rsrc(phi + g.plane, g.plane),
-                                plane_rsrc(phi + 2 * g.plane, g.plane), po, po + g.plane,
+                                phi, phi + g.plane, phi + 2 * g.plane, po, po + g.plane,
                                 po + 2 * g.plane, i, j);
 }
 
@@ -151,7 +150,7 @@ hipError_t launch_batch_step(int prec, int mixed, const void *probs, const TileR
                              hipStream_t s)
 {
     if (prec == GALS_F32) {
-        const Stage<float> st{float(c1), float(c2), float(c3)};
+        const Stage<float> st = make_stage<float>(dt, c1, c2, c3);
         auto kern = mixed == GALS_MIXED_ZERO   ? k_batch_step<float, GALS_MIXED_ZERO, true>
                     : mixed == GALS_MIXED_CELL ? k_batch_step<float, GALS_MIXED_CELL, true>
                                                : k_batch_step<float, GALS_MIXED_CENTRAL, true>;
@@ -159,7 +158,7 @@ hipError_t launch_batch_step(int prec, int mixed, const void *probs, const TileR
                            (const BatchProb<float> *)probs, tiles, ntiles, st, dt,
                            (const float *)tab, (const float *)in, (float *)out);
     } else {
-        const Stage<double> st{c1, c2, c3};
+        const Stage<double> st = make_stage<double>(dt, c1, c2, c3);
         auto kern = mixed == GALS_MIXED_ZERO   ? k_batch_step<double, GALS_MIXED_ZERO, false>
                     : mixed == GALS_MIXED_CELL ? k_batch_step<double, GALS_MIXED_CELL, false>
                                                : k_batch_step<double, GALS_MIXED_CENTRAL, false>;

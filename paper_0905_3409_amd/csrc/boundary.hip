@@ -216,7 +216,7 @@ __device__ __forceinline__ void face_update(const Geom &g, const Vel<T> &p, cons
         const T *ga = sgrad + a * g.plane;
         const T d[2][2] = {{sphi[oc], ga[oc]}, {sphi[oc + s0], ga[oc + s0]}};
         Basis<T> b;
-        basis<T, false>(T(xi[0]), T(g.h[a]), T(g.inv_h[a]), b);
+        basis<T, false>(T(xi[0]), geo_h<T>(g, a), geo_ih<T>(g, a), b);
         H = G[0] = T(0);
 #pragma unroll
         for (int vv = 0; vv < 2; vv++)
@@ -244,7 +244,7 @@ __device__ __forceinline__ void face_update(const Geom &g, const Vel<T> &p, cons
                 ga[vv] = d[vv][1];
                 gb[vv] = d[vv][2];
             }
-            cell_cross(ga, gb, T(g.inv_h[a0]), T(g.inv_h[a1]), cr);
+            cell_cross(ga, gb, geo_ih<T>(g, a0), geo_ih<T>(g, a1), cr);
 #pragma unroll
             for (int vv = 0; vv < 4; vv++) d[vv][3] = cr[vv];
         } else if constexpr (MIX == GALS_MIXED_CENTRAL) {
@@ -252,7 +252,7 @@ __device__ __forceinline__ void face_update(const Geom &g, const Vel<T> &p, cons
             const int c0 = cell[0], n0 = g.nc[a0];
             const int64_t om = oc - (c0 > 0 ? s0 : 0);
             const int64_t o2 = oc + (c0 + 2 <= n0 ? 2 : 1) * s0;
-            const T inv2h = T(0.5 * g.inv_h[a0]);
+            const T inv2h = geo_i2h<T>(g, a0);
             const bool lo = c0 == 0, hi = c0 + 1 == n0;
 #pragma unroll
             for (int row = 0; row < 2; row++) {
@@ -265,8 +265,8 @@ __device__ __forceinline__ void face_update(const Geom &g, const Vel<T> &p, cons
             for (int vv = 0; vv < 4; vv++) d[vv][3] = T(0);
         }
         Basis<T> b0, b1;
-        basis<T, false>(T(xi[0]), T(g.h[a0]), T(g.inv_h[a0]), b0);
-        basis<T, false>(T(xi[1]), T(g.h[a1]), T(g.inv_h[a1]), b1);
+        basis<T, false>(T(xi[0]), geo_h<T>(g, a0), geo_ih<T>(g, a0), b0);
+        basis<T, false>(T(xi[1]), geo_h<T>(g, a1), geo_ih<T>(g, a1), b1);
         hermite2d(d, b0, b1, H, G[0], G[1]);
     }
 #pragma unroll
@@ -373,7 +373,7 @@ static hipError_t face_typed(const gals_ctx *ctx, const Vel<T> &p, const void *s
 {
     const int64_t count = boundary_count(ctx->g);
     const dim3 grid(unsigned((count + kBlock - 1) / kBlock)), block(kBlock);
-    const Stage<T> st{T(c1), T(c2), T(c3)};
+    const Stage<T> st = make_stage<T>(dt, c1, c2, c3);
     const T *sp = (const T *)sphi, *sg = (const T *)sgrad;
     T *dp = (T *)dphi, *dg = (T *)dgrad;
 #define GALS_FACE(D, K)                                                                           \

@@ -238,6 +238,7 @@ int gals_create(gals_ctx **out, int dim, const int64_t *ncell, const double *lo,
             return fail(GALS_EINVAL, "gals_create: more than 2^31 - 1 nodes");
     }
     g.nodes = nodes;
+    geom_finish(g);
     g.pitch = (int64_t(g.n[0]) + 63) / 64 * 64;
     g.plane = g.pitch * g.n[1] * g.n[2];
     if (g.plane * int64_t(prec == GALS_F32 ? 4 : 8) >= (int64_t(1) << 31))

@@ -292,6 +292,7 @@ int gals_batch_create(gals_batch **out, int64_t nprob, const int64_t *ncell, con
             g.top[a] = node_coord(l, nc, g.h[a]);
         }
         g.nodes = int64_t(g.n[0]) * g.n[1];
+        geom_finish(g);
         g.pitch = round_up(g.n[0], 64);
         g.plane = g.pitch * g.n[1];
         if (g.plane * esz >= (int64_t(1) << 31)) {

@@ -20,6 +20,10 @@ constexpr int kJet = 24;             // table stride: the jet, sin and cos of pi
 // used while kx |dx| + ky |dy| stays below this bound (truncation < FP32 rounding)
 constexpr float kTaylorMax = 0.03f;
 
+// A foot counts as outside the domain only when it lies more than kFootTol
+// cells beyond the boundary (see project_foot).
+constexpr double kFootTol = 1e-6;
+
 // Grid geometry, passed by value to kernels.
 struct Geom {
     int dim;
@@ -33,7 +37,50 @@ struct Geom {
     int64_t pitch;   // row pitch in elements
     int64_t plane;   // plane stride in elements
     int64_t nodes;   // n[0]*n[1]*n[2]
+    // derived by geom_finish, so that kernels need no per-wave conversions:
+    double ncd[3];   // nc as double
+    double lastc[3]; // nc - 1 as double (the last cell)
+    // a foot (in cell units) below lowc or above outc is outside the domain:
+    // -kFootTol and nc + kFootTol under GALS_BC_NEUMANN, -inf and +inf (never)
+    // under GALS_BC_EXTRAPOLATE
+    double lowc[3], outc[3];
+    float hf[3], ihf[3], i2hf[3];  // h, 1/h, 1/(2h) rounded to FP32
 };
+
+// Fill the derived fields of a Geom whose bc, nc, h and inv_h are set.
+inline void geom_finish(Geom &g)
+{
+    for (int a = 0; a < 3; a++) {
+        g.ncd[a] = double(g.nc[a]);
+        g.lastc[a] = double(g.nc[a] - 1);
+        const bool proj = g.bc == GALS_BC_NEUMANN;
+        g.lowc[a] = proj ? -kFootTol : -__builtin_inf();
+        g.outc[a] = proj ? double(g.nc[a]) + kFootTol : __builtin_inf();
+        g.hf[a] = float(g.h[a]);
+        g.ihf[a] = float(g.inv_h[a]);
+        g.i2hf[a] = float(0.5 * g.inv_h[a]);
+    }
+}
+
+// h, 1/h and 1/(2h) of axis a in the working precision T.
+template <typename T>
+__device__ __forceinline__ T geo_h(const Geom &g, int a)
+{
+    if constexpr (sizeof(T) == 4) return g.hf[a];
+    else return g.h[a];
+}
+template <typename T>
+__device__ __forceinline__ T geo_ih(const Geom &g, int a)
+{
+    if constexpr (sizeof(T) == 4) return g.ihf[a];
+    else return g.inv_h[a];
+}
+template <typename T>
+__device__ __forceinline__ T geo_i2h(const Geom &g, int a)
+{
+    if constexpr (sizeof(T) == 4) return g.i2hf[a];
+    else return 0.5 * g.inv_h[a];
+}
 
 // Coordinate of node i along an axis: lo + i h with the product rounded before
 // the sum, never fused, on the host and in every kernel alike. A fused value
@@ -66,11 +113,35 @@ struct Vel {
     T vpc[kMaxVecpotModes][21];
 };
 
-// Per-step time factors c(t+dt), c(t), c(t+dt/2) of the three Shu-Osher stages.
+// Per-step factors of the three Shu-Osher stages: the time factors c1, c2,
+// c3 = c(t+dt), c(t), c(t+dt/2), and the stage weights with dt and the time
+// factors folded in, for traces that carry each stage's field without its
+// time factor (w_k = v_k / c_k, R_k = grad v_k / c_k):
+//   x1 = x - e1 w0, x2 = x - q1 w0 - q2 w1, foot = x - f1 w0 - f2 w1 - f3 w2
+// with e1 = dt c1, q1 = dt c1 / 4, q2 = dt c2 / 4, f1 = dt c1 / 6,
+// f2 = dt c2 / 6, f3 = 2 dt c3 / 3, each rounded once to T. Built on the host
+// by make_stage, identically for every launcher.
 template <typename T>
 struct Stage {
     T c1, c2, c3;
+    T e1, q1, q2, f1, f2, f3;
 };
+
+template <typename T>
+inline Stage<T> make_stage(double dt, double c1, double c2, double c3)
+{
+    Stage<T> s;
+    s.c1 = T(c1);
+    s.c2 = T(c2);
+    s.c3 = T(c3);
+    s.e1 = T(dt * c1);
+    s.q1 = T(dt * c1 * 0.25);
+    s.q2 = T(dt * c2 * 0.25);
+    s.f1 = T(dt * c1 / 6.0);
+    s.f2 = T(dt * c2 / 6.0);
+    s.f3 = T(dt * c3 * 2.0 / 3.0);
+    return s;
+}
 
 // One problem of a batch (sine stream-function fields only): its geometry,
 // its velocity tables, where its state and stream tables live, and the wave

@@ -48,6 +48,25 @@ __device__ __forceinline__ void jacobian_chain(const T *A0, const T *A1, const T
                dtT * (A0[k] * T(1.0 / 6.0) + B1[k] * T(1.0 / 6.0) + B2[k] * T(2.0 / 3.0));
 }
 
+// The same chain from the stage Jacobians without their time factors,
+// R_k = A_k / c_k, with dt c_k folded into the weights of Stage:
+// J1 = I - e1 R0; J2 = I - q1 R0 - q2 R1 J1; J = I - f1 R0 - f2 R1 J1 - f3 R2 J2.
+template <typename T, int D>
+__device__ __forceinline__ void jacobian_chain_w(const T *R0, const T *R1, const T *R2,
+                                                 const Stage<T> &st, T *J)
+{
+    T J1[D * D], P1[D * D], J2[D * D], P2[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; k++) J1[k] = T((k % (D + 1)) == 0) - st.e1 * R0[k];
+    matmul_acc<T, D>(R1, J1, P1);
+#pragma unroll
+    for (int k = 0; k < D * D; k++) J2[k] = T((k % (D + 1)) == 0) - st.q1 * R0[k] - st.q2 * P1[k];
+    matmul_acc<T, D>(R2, J2, P2);
+#pragma unroll
+    for (int k = 0; k < D * D; k++)
+        J[k] = T((k % (D + 1)) == 0) - st.f1 * R0[k] - st.f2 * P1[k] - st.f3 * P2[k];
+}
+
 // CHAIN = false (Heun's gradient update) skips the Jacobian chain; J then
 // receives A0, the velocity Jacobian at the node at time t + dt.
 template <typename T, int D, int KIND, bool CHAIN = true>
@@ -113,7 +132,6 @@ __device__ __forceinline__ void heun_gradient(const T *Af, const T *An, T dtT, c
 // evaluated there), so that a foot within rounding of the boundary, e.g. of a
 // node on a face the flow runs along, is not decided by that rounding.
 // ---------------------------------------------------------------------------
-constexpr double kFootTol = 1e-6;
 
 template <int D>
 __device__ __forceinline__ unsigned project_foot(const Geom &g, double *X)
@@ -181,6 +199,15 @@ __device__ __forceinline__ double bload(Rsrc r, unsigned elem, double)
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, elem * 8u, 0, 0));
 }
 
+// Store element `elem` of a plane through a 32-bit byte offset (every plane
+// is below 2 GiB), so the address is the plane's scalar base plus one vector
+// offset.
+template <typename T>
+__device__ __forceinline__ void pstore(T *base, unsigned elem, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + elem * unsigned(sizeof(T))) = v;
+}
+
 // ---------------------------------------------------------------------------
 // Cross derivatives (sec. 2.3, approach (A)) at the two corners c, c+1 of a
 // cell from samples u[0..3] at nodes c-1..c+2 (clamped into [0, N]): central
@@ -231,7 +258,7 @@ __device__ __forceinline__ void gather2d(const Geom &g, Rsrc rphi, Rsrc rgx, Rsr
             ga[v] = d[v][1];
             gb[v] = d[v][2];
         }
-        cell_cross(ga, gb, T(g.inv_h[0]), T(g.inv_h[1]), out);
+        cell_cross(ga, gb, geo_ih<T>(g, 0), geo_ih<T>(g, 1), out);
 #pragma unroll
         for (int v = 0; v < 4; v++) d[v][3] = out[v];
     } else if constexpr (MIX == GALS_MIXED_CENTRAL) {
@@ -243,7 +270,7 @@ __device__ __forceinline__ void gather2d(const Geom &g, Rsrc rphi, Rsrc rgx, Rsr
                          bload(rgy, r1 + i1, T()), bload(rgy, r1 + i2, T())};
         d[0][2] = u0[1]; d[1][2] = u0[2];
         d[2][2] = u1[1]; d[3][2] = u1[2];
-        const T inv2h = T(0.5 * g.inv_h[0]);
+        const T inv2h = geo_i2h<T>(g, 0);
         const bool lo = cx == 0, hi = cx + 1 == g.nc[0];
         diff_pair(u0, lo, hi, inv2h, d[0][3], d[1][3]);
         diff_pair(u1, lo, hi, inv2h, d[2][3], d[3][3]);
@@ -273,7 +300,7 @@ __device__ __forceinline__ void gather3d(const Geom &g, Rsrc rphi, Rsrc rgx, Rsr
             d[v][2] = bload(rgy, o, T());
             d[v][4] = bload(rgz, o, T());
         }
-        const T ih[3] = {T(g.inv_h[0]), T(g.inv_h[1]), T(g.inv_h[2])};
+        const T ih[3] = {geo_ih<T>(g, 0), geo_ih<T>(g, 1), geo_ih<T>(g, 2)};
         // (a, b) = (x, y), (x, z), (y, z) into alpha 3, 5, 6; facet level along
         // the third axis c
         constexpr int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2}, pc[3] = {2, 1, 0};
@@ -313,7 +340,7 @@ __device__ __forceinline__ void gather3d(const Geom &g, Rsrc rphi, Rsrc rgx, Rsr
                             unsigned(c1 + 2 <= g.nc[1] ? c1 + 2 : g.nc[1])};
     const bool xlo = c0 == 0, xhi = c0 + 1 == g.nc[0];
     const bool ylo = c1 == 0, yhi = c1 + 1 == g.nc[1];
-    const T i2hx = T(0.5 * g.inv_h[0]), i2hy = T(0.5 * g.inv_h[1]);
+    const T i2hx = geo_i2h<T>(g, 0), i2hy = geo_i2h<T>(g, 1);
 #pragma unroll
     for (int vz = 0; vz < 2; vz++) {
         const unsigned zo = unsigned(c2 + vz) * S;

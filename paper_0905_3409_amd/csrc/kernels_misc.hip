@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(Geom g, const T *__restrict__ p
     T H, G[D], Hs[D * D];
     Basis<T> b[D];
 #pragma unroll
-    for (int a = 0; a < D; a++) basis<T, true>(T(xi[a]), T(g.h[a]), T(g.inv_h[a]), b[a]);
+    for (int a = 0; a < D; a++) basis<T, true>(T(xi[a]), geo_h<T>(g, a), geo_ih<T>(g, a), b[a]);
     if constexpr (D == 2) {
         T d[4][4];
         gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(grad, g.plane),

@@ -42,8 +42,8 @@ __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st
     gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane), plane_rsrc(gy, g.plane),
                      cell[0], cell[1], d);
     Basis<T> bx, by;
-    basis<T, false>(T(xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
-    basis<T, false>(T(xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
+    basis<T, false>(T(xi[0]), geo_h<T>(g, 0), geo_ih<T>(g, 0), bx);
+    basis<T, false>(T(xi[1]), geo_h<T>(g, 1), geo_ih<T>(g, 1), by);
     T H, Hx, Hy;
     hermite2d(d, bx, by, H, Hx, Hy);
     if (out & 1u) Hx = T(0);
@@ -83,9 +83,9 @@ __device__ __forceinline__ void finish3d(const Geom &g, const Vel<T> &p, const S
     gather3d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane), plane_rsrc(gy, g.plane),
                      plane_rsrc(gz, g.plane), cell[0], cell[1], cell[2], d);
     Basis<T> bx, by, bz;
-    basis<T, false>(T(xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
-    basis<T, false>(T(xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
-    basis<T, false>(T(xi[2]), T(g.h[2]), T(g.inv_h[2]), bz);
+    basis<T, false>(T(xi[0]), geo_h<T>(g, 0), geo_ih<T>(g, 0), bx);
+    basis<T, false>(T(xi[1]), geo_h<T>(g, 1), geo_ih<T>(g, 1), by);
+    basis<T, false>(T(xi[2]), geo_h<T>(g, 2), geo_ih<T>(g, 2), bz);
     T H, Hx, Hy, Hz;
     hermite3d(d, bx, by, bz, H, Hx, Hy, Hz);
     if (out & 1u) Hx = T(0);
@@ -306,8 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_step2d_stream(
     const int j = __builtin_amdgcn_readfirstlane(int(ty) * 4 + int(threadIdx.y));
     if (j >= g.n[1] || i >= g.n[0]) return;
     stream_node<T, MIX, TAYLOR, PSI>(g, p, st, dt, coltab + int64_t(i) * kJet,
-                                rowtab + int64_t(j) * kJet, plane_rsrc(phi, g.plane),
-                                plane_rsrc(grad, g.plane), plane_rsrc(grad + g.plane, g.plane),
+                                rowtab + int64_t(j) * kJet, phi, grad, grad + g.plane,
                                 phi_o, grad_o, grad_o + g.plane, i, j);
 }
 
@@ -329,7 +328,7 @@ static hipError_t launch_stream(const gals_ctx *ctx, const Vel<T> &p, const void
                                 double c1, double c2, double c3, const void *coltab,
                                 const void *rowtab, hipStream_t s)
 {
-    const Stage<T> st{T(c1), T(c2), T(c3)};
+    const Stage<T> st = make_stage<T>(dt, c1, c2, c3);
     const unsigned tiles = unsigned((ctx->g.n[0] + 63) / 64) * unsigned((ctx->g.n[1] + 3) / 4);
     const dim3 grid((tiles + 7u) / 8u * 8u);
     hipLaunchKernelGGL((k_step2d_stream<T, MIX, sizeof(T) == 4, PSI>), grid, dim3(64, 4), 0, s,
@@ -356,7 +355,7 @@ static hipError_t launch_vecpot(const gals_ctx *ctx, const Vel<T> &p, const void
                                 const void *grad, void *phi_o, void *grad_o, double dt,
                                 double c1, double c2, double c3, const void *tab, hipStream_t s)
 {
-    const Stage<T> st{T(c1), T(c2), T(c3)};
+    const Stage<T> st = make_stage<T>(dt, c1, c2, c3);
     const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock + 7) / 8u * 8u;
     hipLaunchKernelGGL((k_step3d_vecpot<T, MIX, true, PSI>), dim3(blocks),
                        dim3(kBlock), 0, s, ctx->g, p, st, dt, (const T *)tab, (const T *)phi,
@@ -369,7 +368,7 @@ static hipError_t launch_typed(const gals_ctx *ctx, const Vel<T> &p, const void 
                                const void *grad, void *phi_o, void *grad_o, double dt, double c1,
                                double c2, double c3, hipStream_t s)
 {
-    const Stage<T> st{T(c1), T(c2), T(c3)};
+    const Stage<T> st = make_stage<T>(dt, c1, c2, c3);
     // rounded up to a multiple of 8 for the XCD band mapping (xcd_block)
     const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock + 7) / 8u * 8u;
     if (ctx->dim == 2) {

@@ -73,13 +73,11 @@ __device__ __forceinline__ T dot4(const T *u, const T *y)
     return u[0] * y[0] + u[1] * y[1] + u[2] * y[2] + u[3] * y[3];
 }
 
-// The 4-jet of s at a node, pre-scaled for Taylor evaluation at an offset
-// (dx, dy): degree 3 for the velocity (-s_y, s_x), degree 2 for its
-// derivatives. a.. = d../2, t.. = d../6.
+// The 4-jet of s at a node for Taylor evaluation at an offset (dx, dy):
+// degree 3 for the velocity (-s_y, s_x), degree 2 for its derivatives.
 template <typename T>
 struct StreamJet {
-    T d10, d01, d20, d11, d02, d30, d21, d12, d03;
-    T a30, a12, a21, a03, a40, a31, a22, a13, a04, t40, t13, t31, t04;
+    T d10, d01, d20, d11, d02, d30, d21, d12, d03, d40, d31, d22, d13, d04;
 };
 
 template <typename T>
@@ -94,34 +92,34 @@ __device__ __forceinline__ void stream_jet(const T *u, const T *y, StreamJet<T> 
     J.d21 = dot4(u + 8, y + 4);
     J.d12 = dot4(u + 4, y + 8);
     J.d03 = dot4(u, y + 12);
-    const T d40 = dot4(u + 16, y), d31 = dot4(u + 12, y + 4), d22 = dot4(u + 8, y + 8);
-    const T d13 = dot4(u + 4, y + 12), d04 = dot4(u, y + 16);
-    const T half = T(0.5), sixth = T(1.0 / 6.0);
-    J.a30 = half * J.d30; J.a12 = half * J.d12; J.a21 = half * J.d21; J.a03 = half * J.d03;
-    J.a40 = half * d40; J.a31 = half * d31; J.a22 = half * d22; J.a13 = half * d13;
-    J.a04 = half * d04;
-    J.t40 = sixth * d40; J.t13 = sixth * d13; J.t31 = sixth * d31; J.t04 = sixth * d04;
+    J.d40 = dot4(u + 16, y);
+    J.d31 = dot4(u + 12, y + 4);
+    J.d22 = dot4(u + 8, y + 8);
+    J.d13 = dot4(u + 4, y + 12);
+    J.d04 = dot4(u, y + 16);
 }
 
 // (s_x, s_y, s_xx, s_xy, s_yy) at offset (dx, dy) from the node, each
-// Taylor polynomial in nested (Horner) form.
+// Taylor polynomial in nested (Horner) form. The factorials go into the
+// offsets (hx = dx/2, tx = dx/3, likewise in y), so the jet is used as built:
+// e.g. s_x = d10 + dx d20 + dx^2 d30/2 + dx^3 d40/6 + ... with
+// dx^2 d30/2 + dx^3 d40/6 = dx hx (d30 + d40 tx).
 template <typename T>
 __device__ __forceinline__ void stream_taylor(const StreamJet<T> &J, T dx, T dy, T &sx, T &sy,
                                               T &sxx, T &sxy, T &syy)
 {
-    // s_x: d10 + dx (d20 + dx (a30 + t40 dx + a31 dy)) + dy (d11 + dx (d21 + a22 dy) + dy (a12 + t13 dy))
-    sx = J.d10 + dx * (J.d20 + dx * (J.a30 + J.t40 * dx + J.a31 * dy)) +
-         dy * (J.d11 + dx * (J.d21 + J.a22 * dy) + dy * (J.a12 + J.t13 * dy));
-    // s_y: d01 + dx (d11 + dx (a21 + t31 dx + a22 dy)) + dy (d02 + dx (d12 + a13 dy) + dy (a03 + t04 dy))
-    sy = J.d01 + dx * (J.d11 + dx * (J.a21 + J.t31 * dx + J.a22 * dy)) +
-         dy * (J.d02 + dx * (J.d12 + J.a13 * dy) + dy * (J.a03 + J.t04 * dy));
-    // second derivatives, degree 2: c0 + dx (cx + cxx dx + cxy dy) + dy (cy + cyy dy)
-    sxx = J.d20 + dx * (J.d30 + J.a40 * dx + T(2) * J.a31 * dy) + dy * (J.d21 + J.a22 * dy);
-    sxy = J.d11 + dx * (J.d21 + J.a31 * dx + T(2) * J.a22 * dy) + dy * (J.d12 + J.a13 * dy);
-    syy = J.d02 + dx * (J.d12 + J.a22 * dx + T(2) * J.a13 * dy) + dy * (J.d03 + J.a04 * dy);
+    const T hx = T(0.5) * dx, hy = T(0.5) * dy;
+    const T tx = T(1.0 / 3.0) * dx, ty = T(1.0 / 3.0) * dy;
+    sx = J.d10 + dx * (J.d20 + hx * (J.d30 + J.d40 * tx + J.d31 * dy)) +
+         dy * (J.d11 + dx * (J.d21 + J.d22 * hy) + hy * (J.d12 + J.d13 * ty));
+    sy = J.d01 + dx * (J.d11 + hx * (J.d21 + J.d31 * tx + J.d22 * dy)) +
+         dy * (J.d02 + dx * (J.d12 + J.d13 * hy) + hy * (J.d03 + J.d04 * ty));
+    sxx = J.d20 + dx * (J.d30 + J.d40 * hx + J.d31 * dy) + dy * (J.d21 + J.d22 * hy);
+    sxy = J.d11 + dx * (J.d21 + J.d31 * hx + J.d22 * dy) + dy * (J.d12 + J.d13 * hy);
+    syy = J.d02 + dx * (J.d12 + J.d22 * hx + J.d13 * dy) + dy * (J.d03 + J.d04 * hy);
 }
 
-// Velocity and its Jacobian at node + (dx, dy), stage factor c: the Taylor
+// Velocity and its Jacobian at node + (dx, dy) without the time factor: the Taylor
 // polynomial of the node's jet when its truncation stays below FP32 rounding
 // (kx |dx| + ky |dy| <= kTaylorMax), the exact modal sum otherwise (and
 // always in FP64). P carries the stream tables S, SQ, SR and kx, ky.
@@ -132,12 +130,12 @@ __device__ __forceinline__ void stream_taylor(const StreamJet<T> &J, T dx, T dy,
 template <typename T, bool TAYLOR, class P>
 __device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J,
                                              const T *__restrict__ U, const T *__restrict__ Y,
-                                             double x0, double y0, T dx, T dy, T c, T *v, T *A)
+                                             double x0, double y0, T dx, T dy, T *v, T *A)
 {
     if (TAYLOR && p.kx * fabs(dx) + p.ky * fabs(dy) <= T(kTaylorMax)) {
         T sx, sy, sxx, sxy, syy;
         stream_taylor(J, dx, dy, sx, sy, sxx, sxy, syy);
-        from_stream(sx, sy, sxx, sxy, syy, c, v, A);
+        from_stream(sx, sy, sxx, sxy, syy, T(1), v, A);
     } else {
         T sx[4], cx[4], sy[4], cy[4];
         constexpr T dmax = T(kShiftMaxLong<T> / kPi);
@@ -151,7 +149,7 @@ __device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J,
             sincos_multiples(T(x0 + double(dx)), sx, cx);
             sincos_multiples(T(y0 + double(dy)), sy, cy);
         }
-        stream_modes(p, sx, cx, sy, cy, c, v, A);
+        stream_modes(p, sx, cx, sy, cy, T(1), v, A);
     }
 }
 
@@ -166,8 +164,9 @@ struct StreamFoot {
     T v0[2], v1[2], v2[2], A0[4], A1[4], A2[4], J[4];
     T d1[2], d2[2];  // stage-2 and stage-3 points minus the node
     unsigned out;    // bit a: the foot left the domain along axis a (Neumann)
+    bool outb[2];    // the same as flags
     int cell[2];
-    double xi[2];
+    T xi[2];         // local coordinate in the cell
     double s[2];     // the foot in cell units, after the boundary treatment
 };
 
@@ -189,38 +188,56 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
         stream_jet(u, y, jet);
     }
     const double x0 = node_coord(g.lo[0], i, g.h[0]), y0 = node_coord(g.lo[1], j, g.h[1]);
-    const T dtT = T(dt);
+    // w_k, R_k: velocity and velocity Jacobian at stage k without the time
+    // factor c_k (Stage carries dt c_k in its weights)
+    T w0[2], R0[4], w1[2], R1[4], w2[2], R2[4];
     // stage 1 at the node, time t + dt
-    from_stream(jet.d10, jet.d01, jet.d20, jet.d11, jet.d02, st.c1, f.v0, f.A0);
+    from_stream(jet.d10, jet.d01, jet.d20, jet.d11, jet.d02, T(1), w0, R0);
     // stage 2 at x1 = x - dt v0, time t
-    f.d1[0] = -dtT * f.v0[0];
-    f.d1[1] = -dtT * f.v0[1];
-    stream_stage<T, TAYLOR>(p, jet, U, Y, x0, y0, f.d1[0], f.d1[1], st.c2, f.v1, f.A1);
+    f.d1[0] = -st.e1 * w0[0];
+    f.d1[1] = -st.e1 * w0[1];
+    stream_stage<T, TAYLOR>(p, jet, U, Y, x0, y0, f.d1[0], f.d1[1], w1, R1);
     // stage 3 at x2 = x - dt (v0 + v1) / 4, time t + dt/2
-    f.d2[0] = -dtT * (T(0.25) * f.v0[0] + T(0.25) * f.v1[0]);
-    f.d2[1] = -dtT * (T(0.25) * f.v0[1] + T(0.25) * f.v1[1]);
-    stream_stage<T, TAYLOR>(p, jet, U, Y, x0, y0, f.d2[0], f.d2[1], st.c3, f.v2, f.A2);
-    if constexpr (CHAIN) jacobian_chain<T, 2>(f.A0, f.A1, f.A2, dtT, f.J);
+    f.d2[0] = -(st.q1 * w0[0] + st.q2 * w1[0]);
+    f.d2[1] = -(st.q1 * w0[1] + st.q2 * w1[1]);
+    stream_stage<T, TAYLOR>(p, jet, U, Y, x0, y0, f.d2[0], f.d2[1], w2, R2);
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+        f.v0[a] = st.c1 * w0[a];
+        f.v1[a] = st.c2 * w1[a];
+        f.v2[a] = st.c3 * w2[a];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        f.A0[k] = st.c1 * R0[k];
+        f.A1[k] = st.c2 * R1[k];
+        f.A2[k] = st.c3 * R2[k];
+    }
+    if constexpr (CHAIN) jacobian_chain_w<T, 2>(R0, R1, R2, st, f.J);
 
-    // foot in cell units, FP64: s = node - dt (v0/6 + v1/6 + 2 v2/3) / h
+    // foot in cell units: s = node - dt (v0/6 + v1/6 + 2 v2/3) / h, the
+    // displacement summed in T from the T velocities (its rounding is of the
+    // order of theirs), the position in FP64
     double s[2];
-    s[0] = double(i) - dt * (double(f.v0[0]) * (1.0 / 6.0) + double(f.v1[0]) * (1.0 / 6.0) +
-                             double(f.v2[0]) * (2.0 / 3.0)) * g.inv_h[0];
-    s[1] = double(j) - dt * (double(f.v0[1]) * (1.0 / 6.0) + double(f.v1[1]) * (1.0 / 6.0) +
-                             double(f.v2[1]) * (2.0 / 3.0)) * g.inv_h[1];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+        s[a] = double(a == 0 ? i : j) -
+               double(st.f1 * w0[a] + st.f2 * w1[a] + st.f3 * w2[a]) * g.inv_h[a];
     f.out = 0;
 #pragma unroll
     for (int a = 0; a < 2; a++) {
-        if (g.bc == GALS_BC_NEUMANN) {
-            // outside only beyond kFootTol cells (project_foot)
-            if (s[a] < -kFootTol) { s[a] = 0.0; f.out |= 1u << a; }
-            else if (s[a] > double(g.nc[a]) + kFootTol) { s[a] = double(g.nc[a]); f.out |= 1u << a; }
-        }
-        // cell index clamped to [0, nc-1], local coordinate unclamped
-        const double fl = fmin(fmax(floor(s[a]), 0.0), double(g.nc[a] - 1));
+        // outside only beyond kFootTol cells (project_foot); the cell index
+        // is clamped to [0, nc-1], the local coordinate is not, except for
+        // a foot outside, which is projected onto the boundary
+        const bool below = s[a] < g.lowc[a], above = s[a] > g.outc[a];
+        const double fl = fmin(fmax(floor(s[a]), 0.0), g.lastc[a]);
         f.cell[a] = int(fl);
-        f.xi[a] = s[a] - fl;
-        f.s[a] = s[a];
+        T xi = T(s[a] - fl);
+        xi = below ? T(0) : xi;
+        f.xi[a] = above ? T(1) : xi;
+        f.outb[a] = below || above;
+        f.out |= unsigned(below || above) << a;
+        f.s[a] = below ? 0.0 : above ? g.ncd[a] : s[a];
     }
 }
 
@@ -230,37 +247,43 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
 template <typename T, int MIX, bool TAYLOR, int PSI = GALS_PSI_SUPERCONSISTENT, class P>
 __device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Stage<T> &st,
                                             double dt, const T *__restrict__ U,
-                                            const T *__restrict__ Y, Rsrc rphi, Rsrc rgx,
-                                            Rsrc rgy, T *__restrict__ phi_o,
+                                            const T *__restrict__ Y,
+                                            const T *__restrict__ phi, const T *__restrict__ gx,
+                                            const T *__restrict__ gy, T *__restrict__ phi_o,
                                             T *__restrict__ gx_o, T *__restrict__ gy_o, int i,
                                             int j)
 {
     StreamFoot<T> f;
     stream_trace<T, TAYLOR, PSI == GALS_PSI_SUPERCONSISTENT>(g, p, st, dt, U, Y, i, j, f);
     T d[4][4];
-    gather2d<T, MIX>(g, rphi, rgx, rgy, f.cell[0], f.cell[1], d);
+    // buffer resources made here, not before the trace, so that they are not
+    // held in scalar registers across it
+    gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane),
+                     plane_rsrc(gy, g.plane), f.cell[0], f.cell[1], d);
     Basis<T> bx, by;
-    basis<T, false>(T(f.xi[0]), T(g.h[0]), T(g.inv_h[0]), bx);
-    basis<T, false>(T(f.xi[1]), T(g.h[1]), T(g.inv_h[1]), by);
+    basis<T, false>(T(f.xi[0]), geo_h<T>(g, 0), geo_ih<T>(g, 0), bx);
+    basis<T, false>(T(f.xi[1]), geo_h<T>(g, 1), geo_ih<T>(g, 1), by);
     T H, Hx, Hy;
     hermite2d(d, bx, by, H, Hx, Hy);
-    if (f.out & 1u) Hx = T(0);
-    if (f.out & 2u) Hy = T(0);
+    if (f.outb[0]) Hx = T(0);
+    if (f.outb[1]) Hy = T(0);
 
-    const int64_t o = int64_t(j) * g.pitch + i;
-    phi_o[o] = H;
+    const unsigned o = unsigned(j) * unsigned(g.pitch) + unsigned(i);
+    pstore(phi_o, o, H);
     if constexpr (PSI == GALS_PSI_HEUN) {
         const double x0 = node_coord(g.lo[0], i, g.h[0]), y0 = node_coord(g.lo[1], j, g.h[1]);
         T vf[2], Af[4], ps[2];
         const T gH[2] = {Hx, Hy};
         stream_stage<T, TAYLOR>(p, f.jet, U, Y, x0, y0, T((f.s[0] - double(i)) * g.h[0]),
-                                T((f.s[1] - double(j)) * g.h[1]), st.c2, vf, Af);
+                                T((f.s[1] - double(j)) * g.h[1]), vf, Af);
+#pragma unroll
+        for (int k = 0; k < 4; k++) Af[k] *= st.c2;
         heun_gradient<T, 2>(Af, f.A0, T(dt), gH, ps);
-        gx_o[o] = ps[0];
-        gy_o[o] = ps[1];
+        pstore(gx_o, o, ps[0]);
+        pstore(gy_o, o, ps[1]);
     } else {
-        gx_o[o] = f.J[0] * Hx + f.J[2] * Hy;
-        gy_o[o] = f.J[1] * Hx + f.J[3] * Hy;
+        pstore(gx_o, o, f.J[0] * Hx + f.J[2] * Hy);
+        pstore(gy_o, o, f.J[1] * Hx + f.J[3] * Hy);
     }
 }
 

@@ -116,20 +116,29 @@ __device__ __forceinline__ void vel_affine(const Vel<T> &p, const double *x, int
 }
 
 // Stream function s = sum_{m,n} S[m][n] sin((m+1) pi x) sin((n+1) pi y).
-// Params is any parameter block with the tables S, SQ, SR.
+// Params is any parameter block with the table S. The y factors carry the
+// wavenumbers (k_n cos, k_n^2 sin), so only S is read: 16 uniform values
+// instead of 48 keep the kernels' scalar registers from spilling.
 template <typename T, class Params>
 __device__ __forceinline__ void stream_modes(const Params &p, const T *sx, const T *cx,
                                              const T *sy, const T *cy, T c, T *v, T *J)
 {
     T fx = 0, fy = 0, fxx = 0, fyy = 0, fxy = 0;
+    T qy[4], ry[4];
+#pragma unroll
+    for (int n = 0; n < 4; n++) {
+        const T kn = T((n + 1) * kPi);
+        qy[n] = kn * cy[n];
+        ry[n] = T((n + 1) * (n + 1) * kPi * kPi) * sy[n];
+    }
 #pragma unroll
     for (int m = 0; m < 4; m++) {
         T P = 0, Q = 0, R = 0;
 #pragma unroll
         for (int n = 0; n < 4; n++) {
-            P += p.S[m][n] * sy[n];   // sum_n S sin(n pi y)
-            Q += p.SQ[m][n] * cy[n];  // d/dy
-            R += p.SR[m][n] * sy[n];  // -d2/dy2
+            P += p.S[m][n] * sy[n];  // sum_n S sin(n pi y)
+            Q += p.S[m][n] * qy[n];  // d/dy
+            R += p.S[m][n] * ry[n];  // -d2/dy2
         }
         const T km = T((m + 1) * kPi);
         const T kc = km * cx[m];
