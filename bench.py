@@ -54,10 +54,13 @@ HBM_PEAK_GBPS = 8000.0
 # build does not emit.)
 VALU_F32_PEAK_TFLOPS = 78.6
 # Floating-point operations per node of the FP32 stream-function step as
-# formulated, FMA = 2: jet 111, stage 1 6, stage 2 80, stage 3 86, Jacobian
-# chain 80, FP64 foot and split 18, cross derivatives 8, Hermite weights 40,
-# bicubic value and gradient 80, gradient update 6.
-ALG_FLOPS_PER_NODE = 515
+# formulated, FMA = 2: jet 98 (14 dot products of 4), stage 1 0 (signs only:
+# dt and the time factors sit in the stage weights), stage 2 75 (offset 2,
+# Taylor test 3, offset scalings 4, Taylor polynomials 66), stage 3 79
+# (offset 6), Jacobian chain 66, foot (displacement in FP32, position in
+# FP64) and split 16, cross derivatives 8, Hermite weights 40, bicubic value
+# and gradient 80, gradient update 6.
+ALG_FLOPS_PER_NODE = 468
 BYTES_PER_NODE = 24  # FP32 state: 3 planes read once + 3 planes written once
 # The cell-based (B) cross derivatives replace the 8 flops of the central
 # differences by 4 edge differences and 4 weighted vertex sums (28 flops).
@@ -91,13 +94,14 @@ SINGLE_KERNEL_SOURCES = ["kernels_step.hip"] + STEP_HEADERS
 BATCH_KERNEL_SOURCES = ["batch.hip"] + STEP_HEADERS
 ADJ_KERNEL_SOURCES = ["adjoint.hip", "reduce.h"] + STEP_HEADERS
 # Floating-point operations per node of the FP32 adjoint step (FMA = 2):
-# trace 381, cross derivatives 8, Hermite weights with second derivatives 60,
+# trace 346 (the forward's 468 less the Hermite part, plus the 12 products
+# that restore the time factors of the stage Jacobians), cross derivatives 8, Hermite weights with second derivatives 60,
 # bicubic value, gradient and Hessian 132, the state adjoint's cell shares
 # 152, seeds 28, reverse Jacobian chain 128, sin/cos multiples at the 3 stage
 # points 112 (from the node's table entries, shifted by angle addition at the
 # two off-node stages), mode terms 546, third derivatives 384, stage-position
 # adjoints 72, accumulation and block reduction 112 (FP64).
-ADJ_FLOPS_PER_NODE = 2115
+ADJ_FLOPS_PER_NODE = 2080
 # read the state (3 x 4 B) and lam_next (3 x 8 B); zero-fill and
 # accumulate lam_prev (3 x 8 B written, and the atomics' read-modify-write)
 ADJ_BYTES_PER_NODE = 12 + 24 + 24 + 24

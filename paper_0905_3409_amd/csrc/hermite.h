@@ -213,12 +213,19 @@ __device__ __forceinline__ void pstore(T *base, unsigned elem, T v)
 // cell from samples u[0..3] at nodes c-1..c+2 (clamped into [0, N]): central
 // differences inside, one-sided 3-point differences at node 0 and node N.
 // ---------------------------------------------------------------------------
-template <typename T>
+// WAVE: the one-sided forms are evaluated only by waves that hold an edge
+// cell (a uniform branch; FP32 2D only: elsewhere the branch costs registers).
+template <typename T, bool WAVE = false>
 __device__ __forceinline__ void diff_pair(const T *u, bool lo_edge, bool hi_edge, T inv2h,
                                           T &d0, T &d1)
 {
-    d0 = (lo_edge ? (T(4) * u[2] - T(3) * u[1] - u[3]) : (u[2] - u[0])) * inv2h;
-    d1 = (hi_edge ? (T(3) * u[2] - T(4) * u[1] + u[0]) : (u[3] - u[1])) * inv2h;
+    T a = u[2] - u[0], b = u[3] - u[1];
+    if (!WAVE || __builtin_amdgcn_ballot_w64(lo_edge || hi_edge)) {
+        a = lo_edge ? T(4) * u[2] - T(3) * u[1] - u[3] : a;
+        b = hi_edge ? T(3) * u[2] - T(4) * u[1] + u[0] : b;
+    }
+    d0 = a * inv2h;
+    d1 = b * inv2h;
 }
 
 // Cross derivative by the cell-based approach (B) (sec. 2.3) on one cell
@@ -272,8 +279,8 @@ __device__ __forceinline__ void gather2d(const Geom &g, Rsrc rphi, Rsrc rgx, Rsr
         d[2][2] = u1[1]; d[3][2] = u1[2];
         const T inv2h = geo_i2h<T>(g, 0);
         const bool lo = cx == 0, hi = cx + 1 == g.nc[0];
-        diff_pair(u0, lo, hi, inv2h, d[0][3], d[1][3]);
-        diff_pair(u1, lo, hi, inv2h, d[2][3], d[3][3]);
+        diff_pair<T, sizeof(T) == 4>(u0, lo, hi, inv2h, d[0][3], d[1][3]);
+        diff_pair<T, sizeof(T) == 4>(u1, lo, hi, inv2h, d[2][3], d[3][3]);
     } else {
         d[0][2] = bload(rgy, r0 + i0, T()); d[1][2] = bload(rgy, r0 + i1, T());
         d[2][2] = bload(rgy, r1 + i0, T()); d[3][2] = bload(rgy, r1 + i1, T());

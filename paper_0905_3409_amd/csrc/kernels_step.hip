@@ -49,18 +49,18 @@ __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st
     if (out & 1u) Hx = T(0);
     if (out & 2u) Hy = T(0);
 
-    const int64_t o = int64_t(j) * g.pitch + i;
-    phi_o[o] = H;
+    const unsigned o = unsigned(j) * unsigned(g.pitch) + unsigned(i);
+    pstore(phi_o, o, H);
     if constexpr (PSI == GALS_PSI_HEUN) {
         T vf[2], Af[4], ps[2];
         const T gH[2] = {Hx, Hy};
         velocity<T, 2, KIND>(p, X, st.c2, vf, Af);
         heun_gradient<T, 2>(Af, J, T(dt), gH, ps);
-        grad_o[o] = ps[0];
-        grad_o[g.plane + o] = ps[1];
+        pstore(grad_o, o, ps[0]);
+        pstore(grad_o + g.plane, o, ps[1]);
     } else {
-        grad_o[o] = J[0] * Hx + J[2] * Hy;
-        grad_o[g.plane + o] = J[1] * Hx + J[3] * Hy;
+        pstore(grad_o, o, J[0] * Hx + J[2] * Hy);
+        pstore(grad_o + g.plane, o, J[1] * Hx + J[3] * Hy);
     }
 }
 
