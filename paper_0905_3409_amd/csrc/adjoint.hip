@@ -168,7 +168,7 @@ __device__ __forceinline__ void emit_scatter(const double (&dbar)[4][4], int c0,
     }
 }
 
-// Four waves per SIMD in FP32: 128 VGPRs (a 28-byte spill) against 134 and
+// Four waves per SIMD in FP32: 128 VGPRs against 134 and
 // three waves by default; 80 -> 68 us per step on the 1024^2 gradient
 // workload. The FP64 kernel would spill heavily and keeps the default.
 template <typename T, int MIX, bool TAYLOR, bool CLEAR>
@@ -358,9 +358,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         int b[4] = {valid ? cell0 : 0x7fffffff, valid ? -cell0 : 0x7fffffff,
                     valid ? cell1 : 0x7fffffff, valid ? -cell1 : 0x7fffffff};
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-            for (int k = 0; k < 4; k++) b[k] = min(b[k], __shfl_xor(b[k], off, 64));
+        for (int k = 0; k < 4; k++) b[k] = wave_min(b[k]);
         if ((threadIdx.x & 63u) == 0) {
             atomicMin(&s_box[0], b[0]);
             atomicMax(&s_box[1], -b[1]);
@@ -395,7 +393,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             scatter(lam_out + fld * g.plane + int64_t(y) * g.pitch + x, v);
         });
     }
-    block_reduce<16, true>(gacc, 0u, partials + int64_t(blockIdx.x) * 16);
+    block_sum16<true>(gacc, partials + int64_t(blockIdx.x) * 16);
 }
 
 // Parameter-derivative partials: sum over blocks in a fixed order.
