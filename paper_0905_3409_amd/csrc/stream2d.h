@@ -122,11 +122,11 @@ __device__ __forceinline__ void stream_taylor(const StreamJet<T> &J, T dx, T dy,
 // Velocity and its Jacobian at node + (dx, dy) without the time factor: the Taylor
 // polynomial of the node's jet when its truncation stays below FP32 rounding
 // (kx |dx| + ky |dy| <= kTaylorMax), the exact modal sum otherwise (and
-// always in FP64). P carries the stream tables S, SQ, SR and kx, ky.
-// Otherwise the modal sum; in FP64, sin and cos of the stage point's angles
-// come from the node's (entries kJetTaylor.. of its table rows U, Y) by angle
-// addition when the offset allows (FP32 keeps sincospi there: the branch is
-// rare, and the extra registers would cost the batched kernel a spill).
+// always in FP64). P carries the stream table S and kx, ky. In the modal
+// sum, sin and cos of the stage point's angles come from the node's (entries
+// kJetTaylor.. of its table rows U, Y) by angle addition with the long series
+// when the offset allows (|pi d| <= 0.1 in FP64, 0.25 in FP32: every stage
+// of a step at CFL ~1 on grids of 32 or more cells), else from sincospi.
 template <typename T, bool TAYLOR, class P>
 __device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J,
                                              const T *__restrict__ U, const T *__restrict__ Y,
@@ -139,7 +139,7 @@ __device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J,
     } else {
         T sx[4], cx[4], sy[4], cy[4];
         constexpr T dmax = T(kShiftMaxLong<T> / kPi);
-        if (sizeof(T) == 8 && fabs(dx) <= dmax && fabs(dy) <= dmax) {
+        if (fabs(dx) <= dmax && fabs(dy) <= dmax) {
             T s, cs;
             shifted_sincos_long(U[kJetTaylor], U[kJetTaylor + 1], dx, s, cs);
             multiples_from(s, cs, sx, cx);

@@ -75,6 +75,27 @@ def test_fp64_stream_both_stage_branches():
     assert rel_psi(g[1], o[1], o[0], hmin) <= TOL64
 
 
+def test_fp32_stream_all_stage_branches():
+    """FP32 stream-function kernel with offsets |pi d| from about 0 to 0.4:
+    Taylor stages where k |d| <= 0.03, the modal sum with angles by angle
+    addition where |pi d| <= 0.25, sincospi beyond; against the oracle."""
+    rng = np.random.default_rng(32)
+    ncell, lo, hi = (41, 37), (-0.1, 0.05), (1.15, 0.95)
+    phi0, psi0 = _random_smooth_state(rng, ncell, lo, hi)
+    params = np.array([0.5, 1, 2, -0.3, 2, 1, 0.2, 3, 3])
+    v = oracle.max_speed(2, ncell, lo, hi, inputs.STREAM_SIN, params, 0.0, 0.0)
+    dt = 0.4 / (np.pi * v)
+    steps = 4
+    args = (2, ncell, lo, hi, inputs.STREAM_SIN, params, 0.0, phi0, psi0, 0.0, dt, steps)
+    g = gpu_advance(*args, dtype="float32")
+    o = oracle_advance(*args)
+    hmin = min((hi[a] - lo[a]) / ncell[a] for a in range(2))
+    tp, tg = fp32_tolerances(o[0], o[1], hmin, steps)
+    ep, eg = rel(g[0], o[0]), rel(g[1], o[1])
+    print(f"fp32 stream, max |pi d| 0.4: phi {ep:.2e} (tol {tp:.2e}) psi {eg:.2e} (tol {tg:.2e})")
+    assert ep <= tp and eg <= tg
+
+
 CASES_3D = [
     ("affine", inputs.AFFINE,
      inputs.affine_params([0.05, 0.0, -0.1], [0.5, 0.5, 0.5],
