@@ -97,13 +97,15 @@ ADJ_KERNEL_SOURCES = ["adjoint.hip", "reduce.h"] + STEP_HEADERS
 # trace 346 (the forward step's jet, stages, chain and foot, 334, plus the 12
 # products that restore the time factors of the stage Jacobians), cross
 # derivatives 8, Hermite weights with second derivatives 60, bicubic value,
-# gradient and Hessian 132, the state adjoint's cell shares 152, seeds 28,
+# gradient and Hessian 132, the state adjoint's cell shares 156, seeds 28,
 # reverse Jacobian chain 128, sin/cos multiples at the 3 stage points 112
 # (from the node's table entries, shifted by angle addition at the two
-# off-node stages), mode terms 546, third derivatives 384, stage-position
-# adjoints 72, accumulation and block reduction 44 (FP64: 16 accumulations,
-# 12 adds of the two halving swaps, 16 of the row sums).
-ADJ_FLOPS_PER_NODE = 2012
+# off-node stages), mode terms 438 (146 a stage: y factors per n, M cos per
+# m, three multiply-adds per mode), third derivatives 376 (188 at each of two
+# stages), stage-position adjoints 72, accumulation and block reduction 44
+# (FP64: 16 accumulations, 12 adds of the two halving swaps, 16 of the row
+# sums).
+ADJ_FLOPS_PER_NODE = 1900
 # read the state (3 x 4 B) and lam_next (3 x 8 B); zero-fill and
 # accumulate lam_prev (3 x 8 B written, and the atomics' read-modify-write)
 ADJ_BYTES_PER_NODE = 12 + 24 + 24 + 24

@@ -28,13 +28,21 @@
 
 namespace gals {
 
-// Third derivatives (s_xxx, s_xxy, s_xyy, s_yyy) of the whole field, from
-// the tables S, SQ = S n pi, SR = S (n pi)^2.
+// Third derivatives (s_xxx, s_xxy, s_xyy, s_yyy) of the whole field from the
+// table S, the y factors carrying the wavenumbers (N cos, N^2 sin, N^3 cos).
 template <typename T, class P>
 __device__ __forceinline__ void third_derivs(const P &p, const T *sx, const T *cx, const T *sy,
                                              const T *cy, T *t)
 {
     t[0] = t[1] = t[2] = t[3] = T(0);
+    T qy[4], ry[4], ty[4];
+#pragma unroll
+    for (int n = 0; n < 4; n++) {
+        const T N = T((n + 1) * kPi);
+        qy[n] = N * cy[n];
+        ry[n] = T((n + 1) * (n + 1) * kPi * kPi) * sy[n];
+        ty[n] = T((n + 1) * (n + 1) * kPi * kPi) * qy[n];
+    }
 #pragma unroll
     for (int m = 0; m < 4; m++) {
         const T M = T((m + 1) * kPi);
@@ -42,9 +50,9 @@ __device__ __forceinline__ void third_derivs(const P &p, const T *sx, const T *c
 #pragma unroll
         for (int n = 0; n < 4; n++) {
             Py += p.S[m][n] * sy[n];
-            Qy += p.SQ[m][n] * cy[n];
-            Ry += p.SR[m][n] * sy[n];
-            Ty += p.SR[m][n] * T((n + 1) * kPi) * cy[n];
+            Qy += p.S[m][n] * qy[n];
+            Ry += p.S[m][n] * ry[n];
+            Ty += p.S[m][n] * ty[n];
         }
         t[0] -= (M * M * M) * cx[m] * Py;
         t[1] -= (M * M) * sx[m] * Qy;
@@ -65,22 +73,30 @@ __device__ __forceinline__ void grad_v_adj(const T *t, const T *Ab, T &gx, T &gy
 // 16 (m, n): with a = -vbar_x, b = vbar_y, e = Abar[3] - Abar[0],
 // the mode term is sin(Mx) (N a cos(Ny) + (N^2 Abar[1] - M^2 Abar[2]) sin(Ny))
 //                + cos(Mx) M (b sin(Ny) + N e cos(Ny)).
+// Per n the y factors are formed once (p = N a cos + N^2 d1 sin, q = d2 sin,
+// r = b sin + N e cos), per m the product M cos(Mx); then each (m, n) takes
+// three multiply-adds: acc += sin(Mx) (p + M^2 q) + M cos(Mx) r.
 template <typename T>
 __device__ __forceinline__ void mode_terms(T c, const T *vb, const T *Ab, const T *sx,
                                            const T *cx, const T *sy, const T *cy, T (&acc)[16])
 {
     const T a = -c * vb[0], b = c * vb[1], e = c * (Ab[3] - Ab[0]);
     const T d1 = c * Ab[1], d2 = -c * Ab[2];
+    T p[4], q[4], r[4], mc[4];
 #pragma unroll
     for (int n = 0; n < 4; n++) {
         const T N = T((n + 1) * kPi);
-        const T ya = N * a * cy[n], yd = N * N * d1 * sy[n], ye = d2 * sy[n];
-        const T yb = b * sy[n], yc = N * e * cy[n];
+        p[n] = (N * a) * cy[n] + (N * N * d1) * sy[n];
+        q[n] = d2 * sy[n];
+        r[n] = b * sy[n] + (N * e) * cy[n];
+    }
 #pragma unroll
-        for (int m = 0; m < 4; m++) {
-            const T M = T((m + 1) * kPi);
-            acc[4 * m + n] += sx[m] * (ya + yd + (M * M) * ye) + cx[m] * (M * (yb + yc));
-        }
+    for (int m = 0; m < 4; m++) mc[m] = T((m + 1) * kPi) * cx[m];
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        const T M2 = T((m + 1) * (m + 1) * kPi * kPi);
+#pragma unroll
+        for (int n = 0; n < 4; n++) acc[4 * m + n] += sx[m] * (p[n] + M2 * q[n]) + mc[m] * r[n];
     }
 }
 
@@ -140,6 +156,8 @@ constexpr int kTileW = 96, kTileH = 12;
 // cell (c0, c1) goes to phi, psi_x, psi_y of that corner and, for the cross
 // derivative phi_xy = D_x psi_y, to psi_y of the difference stencil (central
 // inside, one-sided 3-point at node 0 and node nc). add(field, x, y, value).
+// Per row of the cell the psi_y shares of both corners and of both stencils
+// are summed first: four nodes c0 - 1 .. c0 + 2 inside, three at an edge.
 template <int MIX, class Add>
 __device__ __forceinline__ void emit_scatter(const double (&dbar)[4][4], int c0, int c1, int nc,
                                              double inv2h, Add add)
@@ -149,21 +167,32 @@ __device__ __forceinline__ void emit_scatter(const double (&dbar)[4][4], int c0,
         const int x = c0 + (v & 1), y = c1 + (v >> 1);
         add(0, x, y, dbar[v][0]);
         add(1, x, y, dbar[v][1]);
-        add(2, x, y, dbar[v][2]);
-        if constexpr (MIX == GALS_MIXED_CENTRAL) {
-            const double c = dbar[v][3] * inv2h;
-            if (x == 0) {
-                add(2, 0, y, -3.0 * c);
-                add(2, 1, y, 4.0 * c);
-                add(2, 2, y, -c);
-            } else if (x == nc) {
-                add(2, x, y, 3.0 * c);
-                add(2, x - 1, y, -4.0 * c);
-                add(2, x - 2, y, c);
-            } else {
-                add(2, x + 1, y, c);
-                add(2, x - 1, y, -c);
+        if constexpr (MIX != GALS_MIXED_CENTRAL) add(2, x, y, dbar[v][2]);
+    }
+    if constexpr (MIX == GALS_MIXED_CENTRAL) {
+        const bool lo = c0 == 0, hi = c0 + 1 == nc;  // nc >= 2: not both
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            const int y = c1 + r;
+            const double d0 = dbar[2 * r][2], d1 = dbar[2 * r + 1][2];
+            const double a = dbar[2 * r][3] * inv2h, b = dbar[2 * r + 1][3] * inv2h;
+            // shares of psi_y at nodes c0 - 1, c0, c0 + 1, c0 + 2
+            double t0 = -a, t1 = d0 - b, t2 = d1 + a, t3 = b;
+            if (lo) {
+                t0 = 0.0;
+                t1 = d0 - 3.0 * a - b;
+                t2 = d1 + 4.0 * a;
+                t3 = b - a;
+            } else if (hi) {
+                t0 = b - a;
+                t1 = d0 - 4.0 * b;
+                t2 = d1 + a + 3.0 * b;
+                t3 = 0.0;
             }
+            if (!lo) add(2, c0 - 1, y, t0);
+            add(2, c0, y, t1);
+            add(2, c0 + 1, y, t2);
+            if (!hi) add(2, c0 + 2, y, t3);
         }
     }
 }
