@@ -197,9 +197,10 @@ __device__ __forceinline__ void emit_scatter(const double (&dbar)[4][4], int c0,
     }
 }
 
-// Four waves per SIMD in FP32: 128 VGPRs against 134 and
-// three waves by default; 80 -> 68 us per step on the 1024^2 gradient
-// workload. The FP64 kernel would spill heavily and keeps the default.
+// Four waves per SIMD in FP32 (at most 128 VGPRs): an earlier form took 134
+// and three waves by default, 80 us per step on the 1024^2 gradient workload
+// against 68 at four. The FP64 kernel would spill heavily and keeps the
+// default.
 template <typename T, int MIX, bool TAYLOR, bool CLEAR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     sizeof(T) == 4 ? 4 : 1))) void k_adjoint2d_stream(
