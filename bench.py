@@ -112,12 +112,22 @@ ADJ_BYTES_PER_NODE = 12 + 24 + 24 + 24
 
 
 def kernel_source_hash(files):
+    """Hash of the code a kernel is built from: its sources and the build
+    script, with comments and whitespace removed (an edit of a comment does
+    not change the kernel)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in sorted(files) + ["../build.py"]:
         h.update(name.encode())
-        with open(os.path.join(ROOT, "paper_0905_3409_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_0905_3409_amd", "csrc", name), encoding="utf-8") as fh:
+            text = fh.read()
+        if name.endswith(".py"):
+            text = re.sub(r"#[^\n]*", "", text)
+        else:
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
