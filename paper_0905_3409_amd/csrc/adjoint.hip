@@ -208,10 +208,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     const T *__restrict__ rowtab, const T *__restrict__ phi, const T *__restrict__ grad,
     double *__restrict__ lam_in, double *__restrict__ lam_out, double *__restrict__ partials)
 {
-    const unsigned tiles_x = (unsigned(g.n[0]) + 63u) / 64u;
-    const unsigned tiles = tiles_x * ((unsigned(g.n[1]) + 3u) / 4u);
     unsigned tx, ty;
-    const bool in_grid = xcd_tile(tiles_x, tiles, tx, ty);
+    const bool in_grid = xcd_tile(g, tx, ty);
     const int i = int(tx) * 64 + int(threadIdx.x & 63u);
     const int j = __builtin_amdgcn_readfirstlane(int(ty) * 4 + int(threadIdx.x >> 6));
     double gacc[16];
@@ -474,9 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_heaviside_loss(Geom g, const T *__re
 
 unsigned adjoint_blocks(const gals_ctx *ctx)
 {
-    const unsigned tiles =
-        unsigned((ctx->g.n[0] + 63) / 64) * unsigned((ctx->g.n[1] + 3) / 4);
-    return (tiles + 7u) / 8u * 8u;
+    return (ctx->g.tiles + 7u) / 8u * 8u;
 }
 
 template <typename T, int MIX>

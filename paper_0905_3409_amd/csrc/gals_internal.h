@@ -45,6 +45,9 @@ struct Geom {
     // under GALS_BC_EXTRAPOLATE
     double lowc[3], outc[3];
     float hf[3], ihf[3], i2hf[3];  // h, 1/h, 1/(2h) rounded to FP32
+    // 2D node tiles of 64 x 4: per row group, in all, and floor(2^32 /
+    // tiles_x) (2^32 - 1 for one tile a row) for the division by tiles_x
+    unsigned tiles_x, tiles, tiles_x_magic;
 };
 
 // Fill the derived fields of a Geom whose bc, nc, h and inv_h are set.
@@ -60,6 +63,9 @@ inline void geom_finish(Geom &g)
         g.ihf[a] = float(g.inv_h[a]);
         g.i2hf[a] = float(0.5 * g.inv_h[a]);
     }
+    g.tiles_x = unsigned((g.n[0] + 63) / 64);
+    g.tiles = g.tiles_x * unsigned((g.n[1] + 3) / 4);
+    g.tiles_x_magic = g.tiles_x > 1 ? unsigned((uint64_t(1) << 32) / g.tiles_x) : 0xFFFFFFFFu;
 }
 
 // h, 1/h and 1/(2h) of axis a in the working precision T.

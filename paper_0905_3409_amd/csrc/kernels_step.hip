@@ -298,10 +298,8 @@ __global__ __launch_bounds__(kBlock) void k_step2d_stream(
     const T *__restrict__ rowtab, const T *__restrict__ phi, const T *__restrict__ grad,
     T *__restrict__ phi_o, T *__restrict__ grad_o)
 {
-    const unsigned tiles_x = (unsigned(g.n[0]) + 63u) / 64u;
-    const unsigned tiles = tiles_x * ((unsigned(g.n[1]) + 3u) / 4u);
     unsigned tx, ty;
-    if (!xcd_tile(tiles_x, tiles, tx, ty)) return;
+    if (!xcd_tile(g, tx, ty)) return;
     const int i = int(tx) * 64 + int(threadIdx.x);
     const int j = __builtin_amdgcn_readfirstlane(int(ty) * 4 + int(threadIdx.y));
     if (j >= g.n[1] || i >= g.n[0]) return;
@@ -329,7 +327,7 @@ static hipError_t launch_stream(const gals_ctx *ctx, const Vel<T> &p, const void
                                 const void *rowtab, hipStream_t s)
 {
     const Stage<T> st = make_stage<T>(dt, c1, c2, c3);
-    const unsigned tiles = unsigned((ctx->g.n[0] + 63) / 64) * unsigned((ctx->g.n[1] + 3) / 4);
+    const unsigned tiles = ctx->g.tiles;
     const dim3 grid((tiles + 7u) / 8u * 8u);
     hipLaunchKernelGGL((k_step2d_stream<T, MIX, sizeof(T) == 4, PSI>), grid, dim3(64, 4), 0, s,
                        ctx->g, p, st, dt, (const T *)coltab, (const T *)rowtab, (const T *)phi,

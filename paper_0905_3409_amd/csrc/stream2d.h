@@ -130,7 +130,8 @@ __device__ __forceinline__ void stream_taylor(const StreamJet<T> &J, T dx, T dy,
 template <typename T, bool TAYLOR, class P>
 __device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J,
                                              const T *__restrict__ U, const T *__restrict__ Y,
-                                             double x0, double y0, T dx, T dy, T *v, T *A)
+                                             const Geom &g, int i, int j, double x0,
+                                             double y0, T dx, T dy, T *v, T *A)
 {
     if (TAYLOR && p.kx * fabs(dx) + p.ky * fabs(dy) <= T(kTaylorMax)) {
         T sx, sy, sxx, sxy, syy;
@@ -146,6 +147,13 @@ __device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J,
             shifted_sincos_long(Y[kJetTaylor], Y[kJetTaylor + 1], dy, s, cs);
             multiples_from(s, cs, sy, cy);
         } else {
+            // FP32 forms the node's coordinates only here, off the common path
+            // (x0, y0 unused); FP64 passes them in (forming them here would
+            // cost it scalar-register spills)
+            if constexpr (sizeof(T) == 4) {
+                x0 = node_coord(g.lo[0], i, g.h[0]);
+                y0 = node_coord(g.lo[1], j, g.h[1]);
+            }
             sincos_multiples(T(x0 + double(dx)), sx, cx);
             sincos_multiples(T(y0 + double(dy)), sy, cy);
         }
@@ -187,7 +195,8 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
         }
         stream_jet(u, y, jet);
     }
-    const double x0 = node_coord(g.lo[0], i, g.h[0]), y0 = node_coord(g.lo[1], j, g.h[1]);
+    const double x0 = sizeof(T) == 8 ? node_coord(g.lo[0], i, g.h[0]) : 0.0;
+    const double y0 = sizeof(T) == 8 ? node_coord(g.lo[1], j, g.h[1]) : 0.0;
     // w_k, R_k: velocity and velocity Jacobian at stage k without the time
     // factor c_k (Stage carries dt c_k in its weights)
     T w0[2], R0[4], w1[2], R1[4], w2[2], R2[4];
@@ -196,11 +205,11 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
     // stage 2 at x1 = x - dt v0, time t
     f.d1[0] = -st.e1 * w0[0];
     f.d1[1] = -st.e1 * w0[1];
-    stream_stage<T, TAYLOR>(p, jet, U, Y, x0, y0, f.d1[0], f.d1[1], w1, R1);
+    stream_stage<T, TAYLOR>(p, jet, U, Y, g, i, j, x0, y0, f.d1[0], f.d1[1], w1, R1);
     // stage 3 at x2 = x - dt (v0 + v1) / 4, time t + dt/2
     f.d2[0] = -(st.q1 * w0[0] + st.q2 * w1[0]);
     f.d2[1] = -(st.q1 * w0[1] + st.q2 * w1[1]);
-    stream_stage<T, TAYLOR>(p, jet, U, Y, x0, y0, f.d2[0], f.d2[1], w2, R2);
+    stream_stage<T, TAYLOR>(p, jet, U, Y, g, i, j, x0, y0, f.d2[0], f.d2[1], w2, R2);
 #pragma unroll
     for (int a = 0; a < 2; a++) {
         f.v0[a] = st.c1 * w0[a];
@@ -271,10 +280,10 @@ __device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Sta
     const unsigned o = unsigned(j) * unsigned(g.pitch) + unsigned(i);
     pstore(phi_o, o, H);
     if constexpr (PSI == GALS_PSI_HEUN) {
-        const double x0 = node_coord(g.lo[0], i, g.h[0]), y0 = node_coord(g.lo[1], j, g.h[1]);
         T vf[2], Af[4], ps[2];
         const T gH[2] = {Hx, Hy};
-        stream_stage<T, TAYLOR>(p, f.jet, U, Y, x0, y0, T((f.s[0] - double(i)) * g.h[0]),
+        stream_stage<T, TAYLOR>(p, f.jet, U, Y, g, i, j, node_coord(g.lo[0], i, g.h[0]),
+                                node_coord(g.lo[1], j, g.h[1]), T((f.s[0] - double(i)) * g.h[0]),
                                 T((f.s[1] - double(j)) * g.h[1]), vf, Af);
 #pragma unroll
         for (int k = 0; k < 4; k++) Af[k] *= st.c2;
@@ -288,17 +297,24 @@ __device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Sta
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin by id, and each XCD has its
-// own L2. Give XCD x a contiguous band of tiles (walked row group by row
-// group) so the halo rows a tile gathers were just fetched into the same L2
-// by its neighbours. Returns false for ids past the last tile.
-__device__ __forceinline__ bool xcd_tile(unsigned tiles_x, unsigned tiles, unsigned &tx,
-                                         unsigned &ty)
+// own L2. Give XCD x a contiguous band of the 64 x 4 node tiles (walked row
+// group by row group) so the halo rows a tile gathers were just fetched into
+// the same L2 by its neighbours. Returns false for ids past the last tile.
+// The division by tiles_x is a scalar multiply-high by the host's
+// floor(2^32 / tiles_x) and one correction (exact for every 32-bit t).
+__device__ __forceinline__ bool xcd_tile(const Geom &g, unsigned &tx, unsigned &ty)
 {
-    const unsigned per = (tiles + 7u) / 8u;
+    const unsigned per = (g.tiles + 7u) / 8u;
     const unsigned t = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
-    tx = t % tiles_x;
-    ty = t / tiles_x;
-    return t < tiles;
+    unsigned q = __umulhi(t, g.tiles_x_magic);
+    unsigned r = t - q * g.tiles_x;
+    if (r >= g.tiles_x) {
+        q += 1u;
+        r -= g.tiles_x;
+    }
+    tx = r;
+    ty = q;
+    return t < g.tiles;
 }
 
 // The same for kernels over a flat node range in blocks of kBlock nodes:
