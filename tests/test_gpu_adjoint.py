@@ -102,6 +102,24 @@ def test_step_parameter_derivative_matches_oracle(mixed, period):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_step_parameter_derivative_is_deterministic(dtype):
+    """The 16 parameter partials are summed in a fixed order (lane swaps and
+    row sums within a wave, the waves and then the blocks in order): the
+    same step twice gives the same bits."""
+    import torch
+    params, phi, psi = _case(26)
+    g = _grid(dtype, ncell=(150, 140))
+    g.set_velocity(pkg.STREAM_SIN, params, 1.3)
+    lam = _lam_from_dense(g, np.random.default_rng(27).normal(size=3 * g.num_nodes))
+    st = g.from_numpy(np.resize(phi, g.num_nodes), np.resize(psi, 2 * g.num_nodes))
+    _, a = g.adjoint_step(st, 0.1, 0.03, lam)
+    _, b = g.adjoint_step(st, 0.1, 0.03, lam)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(a).item() == 16
+    assert torch.equal(a, b)
+
+
 def _loss_case(seed=25, steps=11):
     params, phi, psi = _case(seed)
     tgt_params = params.copy()
