@@ -35,8 +35,9 @@ beside the paper's GA-CIR rows, and the 200^3 advance's throughput.
 --workload batched times the many-problem case instead: 512 independent
 grids of round(2^U(5,9)) cells per side, each with its own circles and
 stream function, 256 steps of dt = 2/256 per benchmark step, advanced
-together (one persistent launch per step, the whole advance replayed from a
-captured hipGraph, wave shapes chosen by the autotuner first).
+together (one launch per step over a work list of tiles, the whole advance
+replayed from a captured hipGraph, wave shapes chosen by the autotuner
+first).
 """
 import argparse
 import json

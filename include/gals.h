@@ -269,8 +269,9 @@ int gals_shape_loss(gals_ctx *ctx, const void *phi, const void *phi_ref, double 
 /* ---------------------------------------------------------------------------
  * Batches: many independent 2D grids, each with its own sine stream-function
  * field (GALS_VEL_STREAM_SIN; all share one period), advanced together by one
- * persistent launch per step. The state of all problems is one buffer:
- * problem p's phi plane starts at element offset[p], followed by its psi_x and
+ * launch per step over a flat work list of node tiles of every problem. The
+ * state of all problems is one buffer: problem p's phi plane starts at
+ * element offset[p], followed by its psi_x and
  * psi_y planes (same pitch/plane conventions as a single grid). Throughput
  * layer for the paper's method applied to many small problems; the per-node
  * arithmetic is that of gals_advance, so results agree bit for bit.

@@ -1,9 +1,12 @@
 // Many independent 2D grids with sine stream-function fields advanced by one
-// persistent launch per step. The work list is a flat array of tiles over all
-// problems; XCD x owns a contiguous band of it (so the halo rows a tile
-// gathers were just fetched into the same L2 by its neighbours) and the
-// blocks on that XCD stride through the band. (Per-tile atomic queues were
-// measured as well: no faster, the tiles are even enough.)
+// launch per step. The work list is a flat array of tiles over all problems,
+// one block per tile; XCD x takes a contiguous band of it (so the halo rows a
+// tile gathers were just fetched into the same L2 by its neighbours). Tiles
+// cost unevenly (small grids leave the Taylor range, ragged tiles), and the
+// hardware dispatcher balances them as blocks retire: 306 us per step on 512
+// grids, against 344 us for 8 persistent blocks per CU striding through the
+// bands (their last blocks finished well after the mean) and no better with
+// per-range atomic tile queues.
 // A tile is 4 waves. A wave covers WX x (64/WX) nodes with WX = 64, 32 or 16,
 // or, in the row-major shape, 64 consecutive nodes of the grid in row-major
 // order (no lanes lost to a ragged row end). Per-node arithmetic is the
@@ -73,9 +76,8 @@ __device__ __forceinline__ void batch_tile(const BatchProb<T> &P, unsigned local
 }
 
 template <typename T, int MIX, bool TAYLOR>
-// Eight waves per SIMD in FP32 (64 VGPRs, no spills; the default 73 left
-// room for seven of the eight persistent blocks per CU): 355 -> 345 us per
-// step on 512 grids.
+// Eight waves per SIMD in FP32 (at most 64 VGPRs, no spills; the default 73
+// left room for seven blocks per CU).
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     sizeof(T) == 4 ? 8 : 1))) void k_batch_step(const BatchProb<T> *__restrict__ probs,
                                                        const TileRef *__restrict__ tiles,
@@ -84,22 +86,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
                                                        const T *__restrict__ in,
                                                        T *__restrict__ out)
 {
-    const unsigned xcd = blockIdx.x % 8u, lb = blockIdx.x / 8u, nb = gridDim.x / 8u;
+    // grid: 8 ceil(ntiles / 8) blocks; block b is tile lb of XCD b % 8's band
+    const unsigned xcd = blockIdx.x % 8u, lb = blockIdx.x / 8u;
     const unsigned per = (ntiles + 7u) / 8u;
-    const unsigned t0 = xcd * per;
-    const unsigned t1 = t0 + per < ntiles ? t0 + per : ntiles;
-    for (unsigned t = t0 + lb; t < t1; t += nb) {
-        const TileRef tr = tiles[t];
-        const BatchProb<T> &P = probs[tr.prob];
-        if (P.wx == 64u)
-            batch_tile<T, MIX, TAYLOR, 64u>(P, tr.local, st, dt, tab, in, out);
-        else if (P.wx == 32u)
-            batch_tile<T, MIX, TAYLOR, 32u>(P, tr.local, st, dt, tab, in, out);
-        else if (P.wx == 16u)
-            batch_tile<T, MIX, TAYLOR, 16u>(P, tr.local, st, dt, tab, in, out);
-        else
-            batch_tile<T, MIX, TAYLOR, 0u>(P, tr.local, st, dt, tab, in, out);
-    }
+    const unsigned t = xcd * per + lb;
+    if (lb >= per || t >= ntiles) return;
+    const TileRef tr = tiles[t];
+    const BatchProb<T> &P = probs[tr.prob];
+    if (P.wx == 64u)
+        batch_tile<T, MIX, TAYLOR, 64u>(P, tr.local, st, dt, tab, in, out);
+    else if (P.wx == 32u)
+        batch_tile<T, MIX, TAYLOR, 32u>(P, tr.local, st, dt, tab, in, out);
+    else if (P.wx == 16u)
+        batch_tile<T, MIX, TAYLOR, 16u>(P, tr.local, st, dt, tab, in, out);
+    else
+        batch_tile<T, MIX, TAYLOR, 0u>(P, tr.local, st, dt, tab, in, out);
 }
 
 // Copy the valid nodes of every problem (phi, psi_x, psi_y) from in to out.
@@ -146,9 +147,10 @@ hipError_t launch_batch_tables(int prec, const void *probs_f64, int nprob, int m
 
 hipError_t launch_batch_step(int prec, int mixed, const void *probs, const TileRef *tiles,
                              unsigned ntiles, double dt, double c1, double c2, double c3,
-                             const void *tab, const void *in, void *out, unsigned blocks,
-                             hipStream_t s)
+                             const void *tab, const void *in, void *out, hipStream_t s)
 {
+    if (ntiles == 0) return hipSuccess;
+    const unsigned blocks = (ntiles + 7u) / 8u * 8u;  // one per tile, bands of 8 XCDs
     if (prec == GALS_F32) {
         const Stage<float> st = make_stage<float>(dt, c1, c2, c3);
         auto kern = mixed == GALS_MIXED_ZERO   ? k_batch_step<float, GALS_MIXED_ZERO, true>

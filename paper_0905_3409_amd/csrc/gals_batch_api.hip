@@ -1,7 +1,7 @@
 // Host runtime of the batched C ABI (include/gals.h, gals_batch_*): many
-// independent 2D grids with sine stream-function fields, one persistent
-// launch per step, optional hipGraph capture of a whole advance, and a
-// timing-based choice of the wave shape per grid-size class.
+// independent 2D grids with sine stream-function fields, one launch per
+// step over a work list of tiles, optional hipGraph capture of a whole
+// advance, and a timing-based choice of the wave shape per grid-size class.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -190,7 +190,7 @@ hipError_t enqueue(gals_batch *b, void *state, void *ws, double t0, double dt, i
         const double c2 = b->period > 0 ? cos(M_PI * t / b->period) : 1.0;
         const double c3 = b->period > 0 ? cos(M_PI * (t + 0.5 * dt) / b->period) : 1.0;
         e = launch_batch_step(b->prec, b->mixed, b->d_probs, b->d_tiles, b->ntiles, dt, c1, c2,
-                              c3, tab, bufs[n & 1], bufs[(n + 1) & 1], b->blocks, s);
+                              c3, tab, bufs[n & 1], bufs[(n + 1) & 1], s);
         if (e != hipSuccess) return e;
     }
     if (steps & 1)
@@ -318,9 +318,8 @@ int gals_batch_create(gals_batch **out, int64_t nprob, const int64_t *ncell, con
             delete b;
             return bhip(e, "gals_batch_create: device query");
         }
-        // 8 blocks of 256 threads per CU (7 are resident at the step kernel's
-        // register use; the eighth starts as others finish), a multiple of
-        // the 8 XCDs
+        // the copy-back kernel's grid: 8 blocks of 256 threads per CU, a
+        // multiple of the 8 XCDs (the step kernel takes one block per tile)
         b->blocks = (unsigned(cus) * 8u + 7u) / 8u * 8u;
     } else if (device != -1) {
         delete b;

@@ -232,8 +232,7 @@ hipError_t launch_batch_tables(int prec, const void *probs_f64, int nprob, int m
                                void *tab, hipStream_t s);
 hipError_t launch_batch_step(int prec, int mixed, const void *probs, const TileRef *tiles,
                              unsigned ntiles, double dt, double c1, double c2, double c3,
-                             const void *tab, const void *in, void *out, unsigned blocks,
-                             hipStream_t s);
+                             const void *tab, const void *in, void *out, hipStream_t s);
 hipError_t launch_batch_copy(int prec, const void *probs, const TileRef *tiles, unsigned ntiles,
                              const void *in, void *out, unsigned blocks, hipStream_t s);
 hipError_t launch_eval(const gals_ctx *ctx, const void *phi, const void *grad, const double *pts,

@@ -1,5 +1,5 @@
-"""Batched advance (many independent 2D grids, one persistent launch per
-step) checked against single-grid runs of the same problems, bit for bit,
+"""Batched advance (many independent 2D grids, one launch per step over a
+work list of tiles) checked against single-grid runs of the same problems, bit for bit,
 and in FP64 against the oracle. The per-node arithmetic of the two paths is
 the same code, so any difference is a bug in the batch bookkeeping (tile
 list, offsets, tables, ping-pong) rather than rounding."""
