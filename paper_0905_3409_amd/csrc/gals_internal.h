@@ -48,7 +48,22 @@ struct Geom {
     // 2D node tiles of 64 x 4: per row group, in all, and floor(2^32 /
     // tiles_x) (2^32 - 1 for one tile a row) for the division by tiles_x
     unsigned tiles_x, tiles, tiles_x_magic;
+    unsigned n_magic[3];  // floor(2^32 / n[a]) (2^32 - 1 for one node): see udiv_magic
 };
+
+// x / d and x % d for 32-bit x from m = floor(2^32 / d) (2^32 - 1 for d = 1):
+// floor(x m / 2^32) is the quotient or one less, so a multiply-high and one
+// correction give it exactly for every x.
+__device__ __forceinline__ unsigned udiv_magic(unsigned x, unsigned d, unsigned m, unsigned &r)
+{
+    unsigned q = __umulhi(x, m);
+    r = x - q * d;
+    if (r >= d) {
+        q += 1u;
+        r -= d;
+    }
+    return q;
+}
 
 // Fill the derived fields of a Geom whose bc, nc, h and inv_h are set.
 inline void geom_finish(Geom &g)
@@ -66,6 +81,8 @@ inline void geom_finish(Geom &g)
     g.tiles_x = unsigned((g.n[0] + 63) / 64);
     g.tiles = g.tiles_x * unsigned((g.n[1] + 3) / 4);
     g.tiles_x_magic = g.tiles_x > 1 ? unsigned((uint64_t(1) << 32) / g.tiles_x) : 0xFFFFFFFFu;
+    for (int a = 0; a < 3; a++)
+        g.n_magic[a] = g.n[a] > 1 ? unsigned((uint64_t(1) << 32) / unsigned(g.n[a])) : 0xFFFFFFFFu;
 }
 
 // h, 1/h and 1/(2h) of axis a in the working precision T.

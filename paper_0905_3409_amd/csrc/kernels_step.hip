@@ -23,9 +23,9 @@ __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st
     if (!xcd_block(unsigned((g.nodes + kBlock - 1) / kBlock), blk)) return;
     const unsigned id = blk * kBlock + threadIdx.x;
     if (id >= unsigned(g.nodes)) return;
-    const unsigned nx = unsigned(g.n[0]);
-    const int j = int(id / nx);
-    const int i = int(id - unsigned(j) * nx);
+    unsigned ri;
+    const int j = int(udiv_magic(id, unsigned(g.n[0]), g.n_magic[0], ri));
+    const int i = int(ri);
     const T *gx = grad, *gy = grad + g.plane;
 
     const double x[2] = {node_coord(g.lo[0], i, g.h[0]), node_coord(g.lo[1], j, g.h[1])};
@@ -92,20 +92,21 @@ __device__ __forceinline__ void finish3d(const Geom &g, const Vel<T> &p, const S
     if (out & 2u) Hy = T(0);
     if (out & 4u) Hz = T(0);
 
-    const int64_t o = (int64_t(k) * g.n[1] + j) * g.pitch + i;
-    phi_o[o] = H;
+    const unsigned o = (unsigned(k) * unsigned(g.n[1]) + unsigned(j)) * unsigned(g.pitch) +
+                       unsigned(i);
+    pstore(phi_o, o, H);
     if constexpr (PSI == GALS_PSI_HEUN) {
         T vf[3], Af[9], ps[3];
         const T gH[3] = {Hx, Hy, Hz};
         velocity<T, 3, KIND>(p, X, st.c2, vf, Af);
         heun_gradient<T, 3>(Af, J, T(dt), gH, ps);
-        grad_o[o] = ps[0];
-        grad_o[g.plane + o] = ps[1];
-        grad_o[2 * g.plane + o] = ps[2];
+        pstore(grad_o, o, ps[0]);
+        pstore(grad_o + g.plane, o, ps[1]);
+        pstore(grad_o + 2 * g.plane, o, ps[2]);
     } else {
-        grad_o[o] = J[0] * Hx + J[3] * Hy + J[6] * Hz;
-        grad_o[g.plane + o] = J[1] * Hx + J[4] * Hy + J[7] * Hz;
-        grad_o[2 * g.plane + o] = J[2] * Hx + J[5] * Hy + J[8] * Hz;
+        pstore(grad_o, o, J[0] * Hx + J[3] * Hy + J[6] * Hz);
+        pstore(grad_o + g.plane, o, J[1] * Hx + J[4] * Hy + J[7] * Hz);
+        pstore(grad_o + 2 * g.plane, o, J[2] * Hx + J[5] * Hy + J[8] * Hz);
     }
 }
 
@@ -119,11 +120,10 @@ __global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st
     if (!xcd_block(unsigned((g.nodes + kBlock - 1) / kBlock), blk)) return;
     const unsigned id = blk * kBlock + threadIdx.x;
     if (id >= unsigned(g.nodes)) return;
-    const unsigned nx = unsigned(g.n[0]), ny = unsigned(g.n[1]);
-    const unsigned row = id / nx;
-    const int i = int(id - row * nx);
-    const int k = int(row / ny);
-    const int j = int(row - unsigned(k) * ny);
+    unsigned ri, rj;
+    const unsigned row = udiv_magic(id, unsigned(g.n[0]), g.n_magic[0], ri);
+    const int k = int(udiv_magic(row, unsigned(g.n[1]), g.n_magic[1], rj));
+    const int i = int(ri), j = int(rj);
 
     const double x[3] = {node_coord(g.lo[0], i, g.h[0]), node_coord(g.lo[1], j, g.h[1]),
                          node_coord(g.lo[2], k, g.h[2])};
@@ -233,11 +233,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     if (!xcd_block(unsigned((g.nodes + kBlock - 1) / kBlock), blk)) return;
     const unsigned id = blk * kBlock + threadIdx.x;
     if (id >= unsigned(g.nodes)) return;
-    const unsigned nx = unsigned(g.n[0]), ny = unsigned(g.n[1]);
-    const unsigned row = id / nx;
-    const int i = int(id - row * nx);
-    const int k = int(row / ny);
-    const int j = int(row - unsigned(k) * ny);
+    unsigned ri, rj;
+    const unsigned row = udiv_magic(id, unsigned(g.n[0]), g.n_magic[0], ri);
+    const int k = int(udiv_magic(row, unsigned(g.n[1]), g.n_magic[1], rj));
+    const int i = int(ri), j = int(rj);
 
     const double x[3] = {node_coord(g.lo[0], i, g.h[0]), node_coord(g.lo[1], j, g.h[1]),
                          node_coord(g.lo[2], k, g.h[2])};
