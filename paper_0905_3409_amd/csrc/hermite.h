@@ -178,7 +178,8 @@ __device__ __forceinline__ void split(const Geom &g, const double *X, int *cell,
 // ---------------------------------------------------------------------------
 // Raw buffer loads: one descriptor per plane (base, size in bytes), 32-bit
 // element offsets, reads outside the plane return 0. The host keeps every
-// plane below 4 GiB.
+// plane below 2 GiB, so its size in bytes and every byte offset into it fit a
+// signed 32-bit integer.
 // ---------------------------------------------------------------------------
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 

@@ -99,6 +99,46 @@ def sdf_box(coords, centre, half):
     return phi, np.concatenate(grad)
 
 
+def separable_sines(seed, ncell, lo=None, hi=None):
+    """Factors of phi = prod_a sin(k_a x_a + p_a) on the node axes, with seeded
+    wavenumbers k_a in [2 pi, 6 pi] and phases p_a in [0, 2 pi): returns the
+    per-axis values F_a and derivatives dF_a. A dense state is formed from them
+    by products in a fixed order (``separable_dense``), so any window of it can
+    be rebuilt bit for bit without forming the whole grid, which is what a
+    grid of several hundred million nodes needs."""
+    dim = len(ncell)
+    rng = np.random.default_rng(seed)
+    k = rng.uniform(2.0 * math.pi, 6.0 * math.pi, dim)
+    p = rng.uniform(0.0, 2.0 * math.pi, dim)
+    axes = node_axes(ncell, lo, hi)
+    F = [np.sin(k[a] * axes[a] + p[a]) for a in range(dim)]
+    dF = [k[a] * np.cos(k[a] * axes[a] + p[a]) for a in range(dim)]
+    return F, dF
+
+
+def separable_dense(F, dF, window=None):
+    """Dense phi and psi (x fastest) of the product of the factors over the
+    node ranges window = [(start, stop) per axis] (default: all nodes). The
+    products are taken as (F_x F_y) F_z, with dF_a in place of F_a for
+    psi_a, each a single rounding, so a GPU-side broadcast product in the same
+    order gives the same values."""
+    dim = len(F)
+    if window is None:
+        window = [(0, len(F[a])) for a in range(dim)]
+    sl = [slice(*w) for w in window]
+
+    def prod(fs):
+        v = fs[1][sl[1]][:, None] * fs[0][sl[0]][None, :]
+        if dim == 3:
+            v = fs[2][sl[2]][:, None, None] * v[None, :, :]
+        return v.ravel()
+
+    phi = prod(F)
+    psi = np.concatenate([prod([dF[b] if b == a else F[b] for b in range(dim)])
+                          for a in range(dim)])
+    return phi, psi
+
+
 def gaussian_bump(coords, x0, r0=0.15):
     """exp(-|x - x0|^2) - exp(-r0^2) and its gradient (the smooth initial data
     of the paper's accuracy tests)."""

@@ -121,3 +121,46 @@ def rel_err(a, b):
 
 
 PI = math.pi
+
+
+# ---------------------------------------------------------------------------
+# Grids at the size limit and windows of them
+# ---------------------------------------------------------------------------
+PLANE_LIMIT = 2 ** 31  # bytes: a plane must stay below this
+
+
+def largest_ncell(dim, elem_bytes):
+    """Largest N such that the (N+1)^dim-node grid's plane fits the limit."""
+    n = int((PLANE_LIMIT / elem_bytes) ** (1.0 / dim)) + 64
+    while True:
+        pitch = -(-n // 64) * 64
+        if pitch * n ** (dim - 1) * elem_bytes < PLANE_LIMIT:
+            return n - 1
+        n -= 1
+
+
+def windows(n_nodes, m, dim):
+    """Node ranges of windows of m cells: all corners' extremes and the centre."""
+    lo, mid, hi = 0, (n_nodes - m) // 2, n_nodes - 1 - m
+    if dim == 2:
+        starts = [(lo, lo), (hi, lo), (lo, hi), (hi, hi), (mid, mid)]
+    else:
+        starts = [(lo, lo, lo), (hi, hi, hi), (hi, lo, hi), (lo, hi, lo), (mid, mid, mid)]
+    return [[(s, s + m + 1) for s in st] for st in starts]
+
+
+def interior_mask(win, n_nodes, margin):
+    """Nodes of the window at least margin away from its sides inside the domain."""
+    keep = []
+    for s, e in win:
+        idx = np.arange(s, e)
+        ok = np.ones(e - s, dtype=bool)
+        if s > 0:
+            ok &= idx >= s + margin
+        if e < n_nodes:
+            ok &= idx < e - 1 - margin
+        keep.append(ok)
+    mask = keep[1][:, None] & keep[0][None, :]
+    if len(win) == 3:
+        mask = keep[2][:, None, None] & mask[None, :, :]
+    return mask.ravel()

@@ -66,6 +66,29 @@ def test_create_validation():
     assert L.gals_destroy(None) == pkg.OK
 
 
+@pytest.mark.parametrize("dim,prec,es,n,nbytes", [(2, pkg.F32, 4, 23167, 2147024896),
+                                                 (2, pkg.F64, 8, 16382, 2147352576),
+                                                 (3, pkg.F32, 4, 802, 2145924352),
+                                                 (3, pkg.F64, 8, 639, 2097152000)])
+def test_largest_grids_are_accepted_and_one_more_cell_refused(dim, prec, es, n, nbytes):
+    """A plane (rows padded to 64 nodes) must stay below 2 GiB: 23168^2 FP32
+    nodes take 2147024896 bytes, 16383^2 FP64 nodes (pitch 16384) 2147352576,
+    803^3 FP32 nodes (pitch 832) 2145924352, 640^3 FP64 nodes 2097152000.
+    One more cell per axis crosses the limit. The GPU tests step these grids."""
+    L = pkg.lib()
+    rc, ctx = _ctx(dim=dim, ncell=(n,) * 3, prec=prec)
+    assert rc == pkg.OK
+    nodes = (ctypes.c_int64 * dim)()
+    pitch, plane = ctypes.c_int64(), ctypes.c_int64()
+    assert L.gals_layout(ctx, nodes, ctypes.byref(pitch), ctypes.byref(plane)) == pkg.OK
+    assert tuple(nodes) == (n + 1,) * dim and pitch.value % 64 == 0
+    assert plane.value * es == nbytes < 2 ** 31
+    L.gals_destroy(ctx)
+    rc, _ = _ctx(dim=dim, ncell=(n + 1,) * 3, prec=prec)
+    assert rc == pkg.EINVAL
+    assert b"2 GiB" in L.gals_last_error()
+
+
 @pytest.mark.parametrize("dim,ncell,prec", [(2, (2048, 2048), pkg.F32), (2, (64, 64), pkg.F64),
                                             (3, (256, 256, 256), pkg.F32), (3, (2, 3, 4), pkg.F64)])
 def test_layout_and_workspace(dim, ncell, prec):

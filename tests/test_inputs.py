@@ -30,3 +30,22 @@ def test_leveque_shapes():
     w = inputs.leveque_shape("sphere", 40)
     assert w["steps"] == 100 and w["dt"] == 1 / 40 and w["period"] == 2.5
     assert w["phi0"].min() < 0 < w["phi0"].max()
+
+
+def test_separable_sines_gradient_is_exact():
+    """psi of the separable state is the gradient of phi: central differences
+    of the analytic factors on a fine axis agree to O(h^2)."""
+    for dim in (2, 3):
+        ncell = (4000,) + (7,) * (dim - 1)
+        F, dF = inputs.separable_sines(5, ncell)
+        h = 1.0 / 4000
+        fd = (F[0][2:] - F[0][:-2]) / (2 * h)
+        assert np.max(np.abs(fd - dF[0][1:-1])) <= 1e-4 * np.max(np.abs(dF[0]))
+        phi, psi = inputs.separable_dense(F, dF)
+        n = [c + 1 for c in ncell]
+        P = phi.reshape(tuple(reversed(n)))
+        G = psi.reshape((dim,) + tuple(reversed(n)))
+        # x is the last array axis: psi_x = dF_x times the other factors
+        other = F[1][:, None] if dim == 2 else F[2][:, None, None] * F[1][None, :, None]
+        np.testing.assert_allclose(G[0], other * dF[0], rtol=1e-15, atol=1e-15)
+        np.testing.assert_allclose(P, other * F[0], rtol=1e-15, atol=1e-15)
