@@ -12,7 +12,10 @@ divisions run at the top of their range.
 * properties of the whole output: every value finite and the row padding
   never written;
 * the generic 2D step with v dt an integer number of cells: an exact shift of
-  the data at every node, checked bit for bit on the device.
+  the data at every node, checked bit for bit on the device;
+* a batch whose state spans more than 4 GiB (two of the largest grids around
+  a small one): every problem bit for bit equal to the same grid advanced
+  alone, for each wave shape of the tile list.
 """
 import numpy as np
 import pytest
@@ -26,12 +29,12 @@ from paper_0905_3409_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _fill_state(g, F, dF):
-    """The separable state on the device, products in the generator's order."""
+def _fill(views, F, dF):
+    """The separable state into dense device views (phi, psi_x, psi_y[, psi_z]),
+    products in the generator's order."""
     import torch
-    dev = g._dev()
-    dim = g.dim
-    st = g.empty_state()
+    dim = len(F)
+    dev = views[0].device
     f = [torch.from_numpy(F[a]).to(dev) for a in range(dim)]
     df = [torch.from_numpy(dF[a]).to(dev) for a in range(dim)]
     for a in range(1 + dim):
@@ -39,8 +42,13 @@ def _fill_state(g, F, dF):
         v = fs[1][:, None] * fs[0][None, :]
         if dim == 3:
             v = fs[2][:, None, None] * v[None, :, :]
-        g._grid_view(st[a]).copy_(v)
+        views[a].copy_(v)
         del v
+
+
+def _fill_state(g, F, dF):
+    st = g.empty_state()
+    _fill([g._grid_view(st[a]) for a in range(1 + g.dim)], F, dF)
     return st
 
 
@@ -154,3 +162,42 @@ def test_integer_shift_at_the_largest_2d_grid(dtype, k, axis):
             assert torch.equal(new[:, k:], old[:, :-k])
         else:
             assert torch.equal(new[k:, :], old[:-k, :])
+
+
+@pytest.mark.parametrize("dtype,widths", [("float32", (64, 64, 64, 64)),
+                                          ("float32", (0, 0, 0, 0)),
+                                          ("float32", (16, 16, 16, 16)),
+                                          ("float64", (32, 32, 32, 32))])
+def test_batch_beyond_4_gib_equals_single_grids(dtype, widths):
+    """The third problem's planes start past 4 GiB into the batch state
+    (64-bit problem offsets, 32-bit offsets within a plane); two steps, the
+    second read back from the workspace."""
+    import torch
+    es = 4 if dtype == "float32" else 8
+    n = largest_ncell(2, es)
+    ncells = [(n, n), (700, 1000), (n, n)]
+    print(f"case batch {dtype} widths {widths} ncells {ncells}", flush=True)
+    b = pkg.Batch(ncells, dtype=dtype)
+    b.set_tiles(widths)
+    assert int(b.offset[2]) * es > 2 ** 32
+    rng = np.random.default_rng(16)
+    params = [inputs.stream_modes(rng, 8, (256, 256), 1.0) for _ in ncells]
+    dt, steps = 0.8 / n, 2
+    fields = [inputs.separable_sines(17 + p, ncells[p]) for p in range(len(ncells))]
+    st = b.empty_state()
+    for p in range(len(ncells)):
+        b.set_velocity(p, inputs.STREAM_SIN, params[p], 2.0)
+        _fill(b._views(st, p), *fields[p])
+    b.advance(st, 0.0, dt, steps)
+    torch.cuda.synchronize()
+    for p in range(len(ncells)):
+        print(f"  problem {p} against a single grid", flush=True)
+        g = pkg.Grid(ncells[p], dtype=dtype)
+        g.set_velocity(inputs.STREAM_SIN, params[p], 2.0)
+        sg = _fill_state(g, *fields[p])
+        assert not torch.equal(b._views(st, p)[0], g._grid_view(sg[0]))  # the batch moved it
+        g.advance(sg, 0.0, dt, steps)
+        torch.cuda.synchronize()
+        for a, v in enumerate(b._views(st, p)):
+            assert torch.equal(v, g._grid_view(sg[a])), (p, a)
+        del g, sg
