@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short FP32 advance plus a plain device copy of known size "
                          "(for calibrating rocprofv3 byte counters); prints no JSON")
+    ap.add_argument("--profile-fp64", action="store_true",
+                    help="single workload with --profile: advance the FP64 state instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design "
@@ -215,17 +217,19 @@ def main():
         return g.norms(st, ref, eps, band)  # synchronises
 
     # ---------------------------------------------------------------- FP32
-    g32, ref32, st32 = setup("float32")
     if args.profile:
+        prec = "float64" if args.profile_fp64 else "float32"
+        gp, _, stp = setup(prec)
         steps = args.inner or 64
-        g32.advance(st32, 0.0, w["dt"], steps)
+        gp.advance(stp, 0.0, w["dt"], steps)
         nbytes = 256 << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)  # plain copy: reads and writes exactly 256 MiB
         torch.cuda.synchronize()
-        log(f"profile: {steps} FP32 steps on {nodes} nodes, then a {nbytes} B device copy")
+        log(f"profile: {steps} {prec} steps on {nodes} nodes, then a {nbytes} B device copy")
         return 0
+    g32, ref32, st32 = setup("float32")
     for _ in range(args.warmup):
         bench_step(g32, st32, ref32)
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
