@@ -180,7 +180,10 @@ int gals_set_inflow_data(gals_ctx *ctx, const void *phi_b, const void *grad_b,
  * superconsistency). Step n goes from t0 + n*dt to t0 + (n+1)*dt; times are
  * computed, not accumulated. Departure points may lie any number of cells
  * away (any CFL); feet outside the domain follow the context's boundary
- * treatment. Async. EINVAL on NULL or overlapping state/workspace
+ * treatment. Async: kernel launches and, for an odd step count, one
+ * device-to-device copy back from the workspace, all on `stream`; no
+ * allocation, fill or synchronisation, so a caller may capture the call in
+ * a HIP graph. EINVAL on NULL or overlapping state/workspace
  * pointers, workspace smaller than gals_workspace_bytes, non-finite or
  * non-positive dt, non-finite t0, steps < 0, no velocity set, or a
  * GALS_BC_INFLOW context without inflow data. */

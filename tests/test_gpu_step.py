@@ -239,6 +239,38 @@ def test_side_stream_matches_default_stream():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("dtype,steps", [("float32", 3), ("float64", 2)])
+def test_caller_captured_graph_replays_equal_eager(dtype, steps):
+    """A caller may capture gals_advance (the table kernel, the steps and, for
+    an odd step count, the copy back from the workspace) in a HIP graph: each
+    replay, with eager work and synchronisations between replays, equals the
+    eager advance bit for bit."""
+    import torch
+    w = inputs.stream_circles(seed=5, n=96, steps=64)
+    g = pkg.Grid(w["ncell"], dtype=dtype)
+    g.set_velocity(w["kind"], w["params"], w["period"])
+    init = g.from_numpy(w["phi0"], w["psi0"])
+    eager = init.clone()
+    g.advance(eager, 0.1, w["dt"], steps)  # also allocates the workspace before capture
+    torch.cuda.synchronize()
+    assert not torch.equal(eager, init)
+    st = init.clone()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(graph, stream=side):
+        g.advance(st, 0.1, w["dt"], steps)
+    torch.cuda.synchronize()
+    other = init.clone()
+    for r in range(3):
+        st.copy_(init)
+        torch.cuda.synchronize()
+        graph.replay()
+        g.advance(other, 0.0, w["dt"], 1)  # eager work on the same workspace between replays
+        torch.cuda.synchronize()
+        assert torch.equal(st, eager), f"replay {r}"
+
+
 @pytest.mark.parametrize("steps", [1, 8])
 def test_fp32_against_fp64_oracle_2d(steps):
     w = inputs.stream_circles(seed=5, n=160, steps=128)
