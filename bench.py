@@ -54,6 +54,7 @@ HBM_PEAK_GBPS = 8000.0
 # (The 157.3 TFLOP/s datasheet figure needs packed FP32 instructions, which this
 # build does not emit.)
 VALU_F32_PEAK_TFLOPS = 78.6
+VALU_F32_PACKED_PEAK_TFLOPS = 157.3  # reported beside it, for comparison only
 # Floating-point operations per node of the FP32 stream-function step as
 # formulated, FMA = 2: jet 98 (14 dot products of 4), stage 1 0 (signs only:
 # dt and the time factors sit in the stage weights), stage 2 75 (offset 2,
@@ -280,7 +281,9 @@ def main():
                 "kernel": "k_step2d_stream<float, CENTRAL, taylor>",
                 "flops_per_launch": nodes * ALG_FLOPS_PER_NODE, "avg_launch_us": kernel_us,
                 "hbm_gbps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS,
-                "bytes_per_launch": nodes * BYTES_PER_NODE}
+                "bytes_per_launch": nodes * BYTES_PER_NODE,
+                "packed_fp32_peak": VALU_F32_PACKED_PEAK_TFLOPS,
+                "frac_of_packed_fp32_peak": tflops / VALU_F32_PACKED_PEAK_TFLOPS}
     achieved = gbps
 
     # ------------------------------------------------------- CPU baseline
