@@ -197,13 +197,16 @@ int gals_advance(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int
  * arrays of the context's element type: val[npts], normal[dim*npts] (SoA),
  * curv[npts]; any output may be NULL. Where the gradient is exactly zero the
  * normal and curvature are 0. A point outside the domain evaluates the
- * nearest boundary cell's polynomial. Async. EINVAL on NULL state/points or
- * npts < 0. */
+ * nearest boundary cell's polynomial. Async. EINVAL on NULL state/points,
+ * npts < 0 or npts >= 2^40; npts = 0 does nothing. */
 int gals_eval_points(gals_ctx *ctx, const void *phi, const void *grad, const double *pts,
                      int64_t npts, void *val, void *normal, void *curv, void *stream);
 
-/* max over nodes of |v(x_node, t)| into *out (host). Uses the workspace for
- * partials, synchronises the stream. */
+/* max over nodes of |v(x_node, t)| into *out (host): the largest speed that
+ * sets the CFL number v_max dt / h, which the remark on the time step in
+ * sec. 4 relates to how far a foot may land from its node (feet a cell or
+ * more away are gathered like any other). Uses the workspace for partials,
+ * synchronises the stream. */
 int gals_max_speed(gals_ctx *ctx, double t, double *out, void *workspace,
                    size_t workspace_bytes, void *stream);
 

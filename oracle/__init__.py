@@ -28,8 +28,12 @@ _lib = None
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (OpenMP, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fPIC",
+    """Compile the oracle with gcc (OpenMP, no FMA contraction). -O3 for a
+    fair CPU baseline; the instruction set is x86-64-v3 (AVX2) rather than
+    -march=native because the library is built on one host and run on
+    another (the GPU machine's). Without FMA contraction or reassociation the
+    results do not depend on these flags."""
+    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fPIC",
            "-shared", "-Wall", "-Wextra", "-o", _LIB_PATH, *_SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd))
@@ -64,6 +68,7 @@ def _load():
     lib.orc_grad_cs.argtypes = [L, D, D, D, l, d, i, i, D, D, d, d, l, D, D, d, D, D]
     lib.orc_num_threads.argtypes = []
     lib.orc_set_threads.argtypes = [i]
+    lib.orc_set_sum_order.argtypes = [i]
     _lib = lib
     return lib
 
@@ -99,6 +104,13 @@ def num_threads() -> int:
 def set_threads(n: int) -> None:
     """Threads of the oracle's OpenMP loops from now on."""
     _check(_load().orc_set_threads(int(n)), "set_threads")
+
+
+def set_sum_order(order: int) -> None:
+    """Order of the Hermite sums from now on: 0 (default) the literal sum over
+    every (vertex, derivative) pair, 1 axis by axis. Both evaluate the same
+    definition in FP64; they differ only in rounding."""
+    _check(_load().orc_set_sum_order(int(order)), "set_sum_order")
 
 
 def basis(v: int, alpha: int, deriv: int, x: float) -> float:

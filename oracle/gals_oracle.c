@@ -122,6 +122,60 @@ static double hermite_derivative(int dim, const double *data, const double *h,
     return sum;
 }
 
+/* The same derivative summed in another order, axis by axis: the (v_a,
+ * alpha_a) pairs of the last axis are contracted with their 1D factors
+ * first, then those of the axis before it, and so on. The definition is the
+ * same sum; only the order of the roundings differs. Used solely to measure
+ * how far two correct FP64 evaluations of the interpolant lie apart (the
+ * scale of the parity tolerance); the default is the literal sum above. */
+static double hermite_derivative_axes(int dim, const double *data, const double *h,
+                                      const double *xi, const int *delta)
+{
+    int nv = 1 << dim;
+    /* acc[q], q = sum_a q_a 4^a with q_a = v_a + 2 alpha_a */
+    double acc[64];
+    for (int v = 0; v < nv; v++)
+        for (int alpha = 0; alpha < nv; alpha++) {
+            int q = 0;
+            for (int a = dim - 1; a >= 0; a--)
+                q = 4 * q + (((v >> a) & 1) + 2 * ((alpha >> a) & 1));
+            acc[q] = data[v * nv + alpha];
+        }
+    int size = 1;
+    for (int a = 0; a < dim; a++) size *= 4;
+    for (int a = dim - 1; a >= 0; a--) {
+        size /= 4;  /* entries left after contracting axis a */
+        for (int r = 0; r < size; r++) {
+            double s = 0.0;
+            for (int qa = 0; qa < 4; qa++) {
+                int va = qa & 1, aa = qa >> 1;
+                double f = w_d(va, aa, delta[a], xi[a]);
+                if (aa) f *= h[a];
+                for (int k = 0; k < delta[a]; k++) f /= h[a];
+                s += acc[r + size * qa] * f;
+            }
+            acc[r] = s;
+        }
+    }
+    return acc[0];
+}
+
+static int g_sum_order = 0;
+
+int orc_set_sum_order(int order)
+{
+    if (order < 0 || order > 1) return -1;
+    g_sum_order = order;
+    return 0;
+}
+
+static double hermite_any(int dim, const double *data, const double *h, const double *xi,
+                          const int *delta)
+{
+    if (g_sum_order == 1) return hermite_derivative_axes(dim, data, h, xi, delta);
+    return hermite_derivative(dim, data, h, xi, delta);
+}
+
 int orc_hermite(int dim, const double *data, const double *h, const double *xi,
                 double *val, double *grad, double *hess)
 {
@@ -129,19 +183,19 @@ int orc_hermite(int dim, const double *data, const double *h, const double *xi,
     int delta[MAXD];
     if (val) {
         for (int a = 0; a < dim; a++) delta[a] = 0;
-        *val = hermite_derivative(dim, data, h, xi, delta);
+        *val = hermite_any(dim, data, h, xi, delta);
     }
     if (grad) {
         for (int b = 0; b < dim; b++) {
             for (int a = 0; a < dim; a++) delta[a] = (a == b);
-            grad[b] = hermite_derivative(dim, data, h, xi, delta);
+            grad[b] = hermite_any(dim, data, h, xi, delta);
         }
     }
     if (hess) {
         for (int b = 0; b < dim; b++)
             for (int c = 0; c < dim; c++) {
                 for (int a = 0; a < dim; a++) delta[a] = (a == b) + (a == c);
-                hess[b * dim + c] = hermite_derivative(dim, data, h, xi, delta);
+                hess[b * dim + c] = hermite_any(dim, data, h, xi, delta);
             }
     }
     return 0;
@@ -243,13 +297,13 @@ static int mixed_planes(const grid_t *g, int mode, const double *psi, double *mi
     if (!dyz) return -1;
 #pragma omp parallel for schedule(static)
     for (long idx = 0; idx < N; idx++) {
-        long ijk[MAXD];
+        long ijk[MAXD] = {0, 0, 0};
         node_coords(g, idx, ijk);
         dyz[idx] = diff_axis(g, psi_z, ijk, 1);             /* D_y psi_z */
     }
 #pragma omp parallel for schedule(static)
     for (long idx = 0; idx < N; idx++) {
-        long ijk[MAXD];
+        long ijk[MAXD] = {0, 0, 0};
         node_coords(g, idx, ijk);
         mixed[idx] = diff_axis(g, psi_y, ijk, 0);           /* phi_xy  = D_x psi_y     */
         mixed[N + idx] = diff_axis(g, psi_z, ijk, 0);       /* phi_xz  = D_x psi_z     */
@@ -553,7 +607,7 @@ static void gather_cell(const grid_t *g, const long *cell, const double *phi,
     long N = g->nodes;
     /* plane of the alpha-th datum: 0 phi, single bit -> psi_a, else a mixed plane */
     for (int v = 0; v < nv; v++) {
-        long ijk[MAXD];
+        long ijk[MAXD] = {0, 0, 0};
         for (int a = 0; a < g->dim; a++) ijk[a] = cell[a] + ((v >> a) & 1);
         long idx = node_index(g, ijk);
         for (int alpha = 0; alpha < nv; alpha++) {
@@ -852,7 +906,7 @@ int orc_apply_inflow(int dim, const long *ncell, const double *lo, const double 
     long N = g.nodes;
     int bad = 0;
     for (long idx = 0; idx < N; idx++) {
-        long ijk[MAXD];
+        long ijk[MAXD] = {0, 0, 0};
         double x[MAXD], v[MAXD], G[9];
         int in[MAXD], nin = 0, axis = -1;
         node_coords(&g, idx, ijk);
@@ -1010,7 +1064,7 @@ double orc_max_speed(int dim, const long *ncell, const double *lo, const double 
     if (make_grid(&g, dim, ncell, lo, hi)) return -1.0;
     double best = 0.0;
     for (long idx = 0; idx < g.nodes; idx++) {
-        long ijk[MAXD];
+        long ijk[MAXD] = {0, 0, 0};
         double x[MAXD], v[MAXD], G[9];
         node_coords(&g, idx, ijk);
         for (int a = 0; a < dim; a++) x[a] = g.lo[a] + (double)ijk[a] * g.h[a];

@@ -150,6 +150,12 @@ int orc_grad_cs(const long *ncell, const double *lo, const double *hi, const dou
 /* Number of OpenMP threads the oracle runs with (1 without OpenMP). */
 /* Threads of the OpenMP loops from now on (n >= 1). */
 int orc_set_threads(int n);
+/* Order of the Hermite sums from now on: 0 (default) the literal sum over
+ * every (vertex, derivative) pair of eq. (p-cubic_interpolant); 1 the same
+ * sum contracted axis by axis (last axis first). Both are exact FP64
+ * evaluations of one definition that round in different orders; the second
+ * exists to measure that difference. */
+int orc_set_sum_order(int order);
 int orc_num_threads(void);
 
 #ifdef __cplusplus

@@ -5,20 +5,20 @@
 
 namespace gals {
 
+constexpr int64_t kEvalMaxBlocks = int64_t(1) << 20;
+
 // ---------------------------------------------------------------------------
 // Point evaluation (sec. 3.2): n = grad H / |grad H|, and the curvature
 // kappa = div n = (|g|^2 tr(Hess) - g^T Hess g) / |g|^3, which is eq.
 // (curvature) in 2D and the sum of the principal curvatures in 3D.
 // ---------------------------------------------------------------------------
 template <typename T, int D, int MIX>
-__global__ __launch_bounds__(kBlock) void k_eval(Geom g, const T *__restrict__ phi,
-                                                 const T *__restrict__ grad,
-                                                 const double *__restrict__ pts, int64_t npts,
-                                                 T *__restrict__ val, T *__restrict__ normal,
-                                                 T *__restrict__ curv)
+__device__ __forceinline__ void eval_point(const Geom &g, const T *__restrict__ phi,
+                                           const T *__restrict__ grad,
+                                           const double *__restrict__ pts, int64_t npts,
+                                           int64_t id, T *__restrict__ val,
+                                           T *__restrict__ normal, T *__restrict__ curv)
 {
-    const int64_t id = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (id >= npts) return;
     double X[D];
 #pragma unroll
     for (int a = 0; a < D; a++) X[a] = pts[a * npts + id];
@@ -59,12 +59,28 @@ __global__ __launch_bounds__(kBlock) void k_eval(Geom g, const T *__restrict__ p
     if (curv) curv[id] = ok ? (g2 * tr - gHg) / (g2 * nrm) : T(0);
 }
 
+template <typename T, int D, int MIX>
+__global__ __launch_bounds__(kBlock) void k_eval(Geom g, const T *__restrict__ phi,
+                                                 const T *__restrict__ grad,
+                                                 const double *__restrict__ pts, int64_t npts,
+                                                 T *__restrict__ val, T *__restrict__ normal,
+                                                 T *__restrict__ curv)
+{
+    // grid-stride over the points: the launch caps its grid (eval_typed), so
+    // any count the entry point accepts fits the launch's work-item count
+    for (int64_t id = int64_t(blockIdx.x) * kBlock + threadIdx.x; id < npts;
+         id += int64_t(gridDim.x) * kBlock)
+        eval_point<T, D, MIX>(g, phi, grad, pts, npts, id, val, normal, curv);
+}
+
 template <typename T, int MIX>
 static hipError_t eval_typed(const gals_ctx *ctx, const void *phi, const void *grad,
                              const double *pts, int64_t npts, void *val, void *normal, void *curv,
                              hipStream_t s)
 {
-    const unsigned blocks = unsigned((npts + kBlock - 1) / kBlock);
+    // at most 2^20 blocks of 256 (2^28 work items); larger counts loop
+    const int64_t want = (npts + kBlock - 1) / kBlock;
+    const unsigned blocks = unsigned(want < kEvalMaxBlocks ? want : kEvalMaxBlocks);
     if (ctx->dim == 2)
         hipLaunchKernelGGL((k_eval<T, 2, MIX>), dim3(blocks), dim3(kBlock), 0, s, ctx->g,
                            (const T *)phi, (const T *)grad, pts, npts, (T *)val, (T *)normal,

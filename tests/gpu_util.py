@@ -39,7 +39,13 @@ def rel_psi(g_psi, o_psi, o_phi, hmin):
     |phi|) moves psi by u |phi| / h; two correct implementations that round
     differently therefore differ by a few u max(|psi|, |phi|/h)."""
     scale = max(np.max(np.abs(o_psi)), np.max(np.abs(o_phi)) / hmin)
-    return float(np.max(np.abs(g_psi - o_psi)) / scale)
+    diff = float(np.max(np.abs(g_psi - o_psi)))
+    # the plain normwise measure beside it, for the record (two FP64 orders of
+    # the oracle's own Hermite sum differ by as much on that measure)
+    plain = diff / max(float(np.max(np.abs(o_psi))), 1e-300)
+    print(f"    psi: max|d|/max|psi| {plain:.2e}, on the max(|psi|,|phi|/h) scale "
+          f"{diff / scale:.2e}", flush=True)
+    return diff / scale
 
 
 def fp32_tolerances(phi_ref, psi_ref, hmin, steps, k=32.0):

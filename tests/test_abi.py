@@ -172,6 +172,13 @@ def test_advance_validation_on_host_only_context():
     assert L.gals_eval_points(ctx, phi, grad, None, 0, None, None, None, None) == pkg.OK
     assert L.gals_eval_points(ctx, phi, grad, None, 5, None, None, None, None) == pkg.EINVAL
     assert L.gals_eval_points(ctx, phi, grad, w, -1, None, None, None, None) == pkg.EINVAL
+    # point counts: 2^40 and beyond are refused before the device check; one
+    # below passes validation (the kernel strides over any count, so the
+    # launch's 32-bit work-item count never wraps)
+    assert L.gals_eval_points(ctx, phi, grad, w, 1 << 40, None, None, None, None) == pkg.EINVAL
+    assert b"too many points" in L.gals_last_error()
+    assert L.gals_eval_points(ctx, phi, grad, w, (1 << 40) - 1, None, None, None, None) == pkg.EINVAL
+    assert b"host-only" in L.gals_last_error()
     out = (ctypes.c_double * 8)()
     assert L.gals_norms(ctx, phi, grad, phi, grad, 0.0, 0.1, out, w, ws.value, None) == pkg.EINVAL
     assert L.gals_max_speed(ctx, 0.0, out, w, 8, None) == pkg.EINVAL

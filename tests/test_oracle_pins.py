@@ -748,6 +748,122 @@ def test_norms_brute_force():
     assert out[7] == pytest.approx(np.abs(phr).max())
 
 
+def _two_discs(n, c1, r1, c2, r2):
+    """Signed distances (and gradients) of two discs on the unit square's
+    n^2-cell grid, with eps = 1.5 h and band = 3 h as the benchmark uses."""
+    h = 1.0 / n
+    co = inputs.node_grid((n, n))
+    p1, g1 = inputs.sdf_union(co, [c1], [r1])
+    p2, g2 = inputs.sdf_union(co, [c2], [r2])
+    return oracle.norms(2, (n, n), [0, 0], [1, 1], p1, g1, p2, g2, 1.5 * h, 3 * h), h
+
+
+@pytest.mark.parametrize("n", [64, 128, 256])
+def test_l1_shape_error_of_concentric_circles_is_the_annulus_area(n):
+    """Geometric meaning of the L1 shape error (sec. 6.1 measures errors of
+    the level set; the shape error is the smoothed area between the two
+    interfaces). For signed distances of concentric circles of radii r and
+    r + d, H_eps(rho - r) - H_eps(rho - r - d) is the integral over a in
+    [r, r + d] of the smoothing kernel H_eps' centred at a; the kernel is even
+    with unit mass, so the area integral of each shell is 2 pi a, and the
+    whole integral is pi ((r + d)^2 - r^2) for any eps below r: exactly the
+    area of the annulus. Also: phi - phi_ref = d everywhere (max-norm and band
+    error), and the gradients are equal."""
+    c, r, d = np.array([0.4817, 0.5233]), 0.2, 0.013
+    out, h = _two_discs(n, c, r, c, r + d)
+    exact = PI * ((r + d) ** 2 - r ** 2)
+    assert abs(out[2] - exact) <= 1e-4 * exact, (out[2], exact)
+    assert out[0] == pytest.approx(d, rel=1e-13)
+    assert out[3] == pytest.approx(d, rel=1e-13)
+    assert out[1] == 0.0
+
+
+@pytest.mark.parametrize("n", [64, 128, 256])
+def test_disc_volume_carries_the_known_smoothing_bias(n):
+    """Volume prod(h) sum H_eps(-phi) of a disc of radius r: splitting
+    H_eps(r - rho) into the indicator of rho < r and an odd remainder in
+    u = rho - r, the remainder integrates to 0 against r and to
+    2 int_0^eps u H_eps(-u) du against u, so the volume is
+    pi r^2 + 4 pi int_0^eps u H_eps(-u) du = pi r^2 + pi eps^2 (1/3 - 2/pi^2)
+    for the smoothed Heaviside with the sin(pi s/eps)/pi term (with the
+    opposite sign of that term the bias would be pi eps^2 (1/3 + 2/pi^2),
+    four times larger)."""
+    c, r, d = np.array([0.4817, 0.5233]), 0.2, 0.013
+    out, h = _two_discs(n, c, r, c, r + d)
+    eps = 1.5 * h
+    for vol, rr in ((out[4], r), (out[5], r + d)):
+        pred = PI * rr * rr + PI * eps * eps * (1.0 / 3.0 - 2.0 / PI ** 2)
+        assert abs(vol - pred) <= 2e-5 * pred, (n, vol, pred)
+
+
+def test_l1_shape_error_of_offset_discs_converges_to_symmetric_difference():
+    """Two discs of radius r whose centres are s apart: as h -> 0 (eps = 1.5 h
+    -> 0) the L1 shape error tends to the area of their symmetric difference,
+    2 (pi r^2 - lens), lens = 2 r^2 acos(s / 2r) - (s/2) sqrt(4 r^2 - s^2).
+    Where the two circles cross, the smoothing differs from the sharp
+    indicator over an eps x eps patch, so the error falls with h."""
+    c, r, s = np.array([0.4817, 0.5233]), 0.2, 0.05
+    lens = 2 * r * r * math.acos(s / (2 * r)) - 0.5 * s * math.sqrt(4 * r * r - s * s)
+    sym = 2.0 * (PI * r * r - lens)
+    errs = []
+    for n in (64, 128, 256, 512):
+        out, h = _two_discs(n, c, r, c + np.array([s, 0.0]), r)
+        errs.append(abs(out[2] - sym) / sym)
+    assert errs[0] < 1e-3 and errs[-1] < 2e-5, errs
+    assert errs[-1] < errs[0] / 10, errs
+
+
+def test_hermite_sum_orders_agree_to_rounding():
+    """The interpolant evaluated as the literal sum over (vertex, derivative)
+    pairs and contracted axis by axis: one definition, two orders of
+    rounding. Value and gradient agree to a few units of FP64 roundoff of
+    the terms' magnitude, for random data and points, in 2D and 3D."""
+    rng = np.random.default_rng(77)
+    for dim in (2, 3):
+        nv = 1 << dim
+        for _ in range(50):
+            data = rng.normal(size=(nv, nv))
+            h = rng.uniform(0.01, 1.0, dim)
+            xi = rng.uniform(-0.5, 1.5, dim)
+            a = oracle.hermite(dim, data, h, xi)
+            oracle.set_sum_order(1)
+            try:
+                b = oracle.hermite(dim, data, h, xi)
+            finally:
+                oracle.set_sum_order(0)
+            mag = np.abs(data).sum() * 4.0 ** dim
+            assert abs(a[0] - b[0]) <= 1e-15 * mag
+            assert np.abs(a[1] - b[1]).max() <= 1e-15 * mag / h.min()
+
+
+def test_psi_spread_of_two_sum_orders_at_the_benchmark_size():
+    """How far apart two correct FP64 evaluations of the 2048^2 benchmark
+    step lie (the scale of the parity tolerance for psi): the interpolant's
+    gradient sums terms of size |phi|/h (about 700 max|psi| here) to a result
+    of size |psi|, so rounding the terms in another order moves psi by about
+    u max|phi|/h. After two steps the literal and the axis-by-axis orders
+    differ in psi by more than 1e-13 of max|psi| (measured 1.15e-12), yet by
+    only a few u on the scale max(max|psi|, max|phi|/h)."""
+    w = inputs.stream_circles()
+    res = []
+    for order in (0, 1):
+        oracle.set_sum_order(order)
+        try:
+            res.append(oracle.advance(2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"],
+                                      w["period"], w["phi0"], w["psi0"], 0.0, w["dt"], 2))
+        finally:
+            oracle.set_sum_order(0)
+    (p0, g0), (p1, g1) = res
+    h = 1.0 / w["ncell"][0]
+    plain = np.abs(g1 - g0).max() / np.abs(g0).max()
+    scaled = np.abs(g1 - g0).max() / max(np.abs(g0).max(), np.abs(p0).max() / h)
+    print(f"two FP64 sum orders, 2048^2, 2 steps: phi {np.abs(p1 - p0).max() / np.abs(p0).max():.2e} "
+          f"psi plain {plain:.2e} psi/scale {scaled:.2e}")
+    assert np.abs(p1 - p0).max() <= 1e-14 * np.abs(p0).max()
+    assert plain > 1e-13
+    assert scaled <= 1e-14
+
+
 def test_max_speed_brute_force():
     w = inputs.stream_circles(seed=5, n=32, steps=64)
     s = oracle.max_speed(2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"],
