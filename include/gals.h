@@ -190,6 +190,25 @@ int gals_set_inflow_data(gals_ctx *ctx, const void *phi_b, const void *grad_b,
 int gals_advance(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int64_t steps,
                  void *workspace, size_t workspace_bytes, void *stream);
 
+/* Size of the library's static device scratch used by gals_advance_noalloc
+ * (64 MiB per GPU the library runs on, held until the process ends). */
+#define GALS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * advance as gals_advance (same kernels, same results bit for bit) with no
+ * workspace argument. The ping-pong state copy and the velocity tables live
+ * in the library's static device scratch of GALS_NOALLOC_SCRATCH_BYTES per
+ * GPU; the call allocates and frees nothing. The caller still owns phi and
+ * grad. Every call on one GPU shares that GPU's scratch, which keeps the last
+ * call's contents (nothing in it needs to start at zero): calls that overlap
+ * on one GPU (different streams, different host threads) race and must be
+ * ordered by the caller, e.g. on one stream. EINVAL as gals_advance, and
+ * when gals_workspace_bytes of the context exceeds the scratch (2D FP32
+ * grids fit up to about 2048^2 cells, FP64 up to about 1440^2). Async. */
+int gals_advance_noalloc(gals_ctx *ctx, void *phi, void *grad, double t0, double dt,
+                         int64_t steps, void *stream);
+
 /* Value, unit normal and curvature of the Hermite interpolant at npts points
  * (sec. 3.2, eqs. surface_normal and curvature; in 3D the curvature is the
  * divergence of the normal, i.e. the sum of the principal curvatures).

@@ -37,7 +37,8 @@ EXPORTS = ("gals_create", "gals_destroy", "gals_layout", "gals_workspace_bytes",
            "gals_batch_set_tiles", "gals_batch_get_tiles", "gals_batch_advance",
            "gals_batch_autotune", "gals_checkpoint_bytes", "gals_advance_save",
            "gals_adjoint_workspace_bytes", "gals_adjoint", "gals_adjoint_step",
-           "gals_shape_loss", "gals_set_psi_update", "gals_set_inflow_data")
+           "gals_shape_loss", "gals_set_psi_update", "gals_set_inflow_data",
+           "gals_advance_noalloc")
 
 _lib = None
 
@@ -65,6 +66,7 @@ def lib():
     L.gals_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
     L.gals_set_velocity.argtypes = [vp, i, PD, i64, d]
     L.gals_advance.argtypes = [vp, vp, vp, d, d, i64, vp, sz, vp]
+    L.gals_advance_noalloc.argtypes = [vp, vp, vp, d, d, i64, vp]
     L.gals_eval_points.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp]
     L.gals_max_speed.argtypes = [vp, d, PD, vp, sz, vp]
     L.gals_norms.argtypes = [vp, vp, vp, vp, vp, d, d, PD, vp, sz, vp]
@@ -244,6 +246,17 @@ class Grid:
                                  ctypes.c_void_p(state[1].data_ptr()), float(t0), float(dt),
                                  int(steps), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                  _stream_handle(stream, self._dev())))
+        return state
+
+    def advance_noalloc(self, state, t0, dt, steps, stream=None):
+        """As advance, through the entry point that allocates nothing: its
+        scratch is the library's static device array (calls on one GPU share
+        it, so order them on one stream)."""
+        self._check_state(state)
+        check(lib().gals_advance_noalloc(self._ctx, ctypes.c_void_p(state[0].data_ptr()),
+                                         ctypes.c_void_p(state[1].data_ptr()), float(t0),
+                                         float(dt), int(steps),
+                                         _stream_handle(stream, self._dev())))
         return state
 
     def eval_points(self, state, pts, stream=None):

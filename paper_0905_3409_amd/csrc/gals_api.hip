@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "gals_internal.h"
@@ -192,6 +193,51 @@ void fill_vel(Vel<T> &v, int kind, int dim, const double *p, int64_t np)
 
 bool is_int_in(double x, int lo, int hi) { return x == floor(x) && x >= lo && x <= hi; }
 
+// Checks shared by the advances: velocity and inflow data set, finite
+// positive dt, finite t0, steps >= 0, state pointers aligned to the element.
+int check_advance_args(const gals_ctx *ctx, const void *phi, const void *grad, double t0,
+                       double dt, int64_t steps, const char *what)
+{
+    if (!ctx->vel_set) return fail(GALS_EINVAL, "%s: no velocity set", what);
+    if (ctx->inflow && !ctx->inflow_phi)
+        return fail(GALS_EINVAL, "%s: GALS_BC_INFLOW without gals_set_inflow_data", what);
+    if (!isfinite(dt) || !(dt > 0.0)) return fail(GALS_EINVAL, "%s: dt must be finite and > 0", what);
+    if (!isfinite(t0)) return fail(GALS_EINVAL, "%s: t0 must be finite", what);
+    if (steps < 0) return fail(GALS_EINVAL, "%s: steps < 0", what);
+    const size_t es = elem_size(ctx);
+    if (!aligned(phi, es) || !aligned(grad, es)) return fail(GALS_EINVAL, "%s: misaligned pointer", what);
+    return GALS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free advance: a static device array, one copy per
+// GPU the library runs on, held until the process ends. In host code the
+// array's name is only a host-side stand-in; its device address on each GPU
+// comes from hipGetSymbolAddress with that GPU current, resolved on the entry
+// point's first call there and kept per device. Every call on a GPU shares
+// that GPU's copy.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = GALS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_addr[kMaxScratchDevices];
+
+// Device address of `scratch` on `dev`, which must be the current device.
+hipError_t scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -377,15 +423,10 @@ int gals_advance(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int
 {
     if (!ctx) return fail(GALS_EINVAL, "gals_advance: NULL context");
     if (!phi || !grad || !workspace) return fail(GALS_EINVAL, "gals_advance: NULL pointer");
-    if (!ctx->vel_set) return fail(GALS_EINVAL, "gals_advance: no velocity set");
-    if (ctx->inflow && !ctx->inflow_phi)
-        return fail(GALS_EINVAL, "gals_advance: GALS_BC_INFLOW without gals_set_inflow_data");
-    if (!isfinite(dt) || !(dt > 0.0)) return fail(GALS_EINVAL, "gals_advance: dt must be finite and > 0");
-    if (!isfinite(t0)) return fail(GALS_EINVAL, "gals_advance: t0 must be finite");
-    if (steps < 0) return fail(GALS_EINVAL, "gals_advance: steps < 0");
+    int rc = check_advance_args(ctx, phi, grad, t0, dt, steps, "gals_advance");
+    if (rc != GALS_OK) return rc;
     const size_t es = elem_size(ctx);
-    if (!aligned(phi, es) || !aligned(grad, es) || !aligned(workspace, 256))
-        return fail(GALS_EINVAL, "gals_advance: misaligned pointer");
+    if (!aligned(workspace, 256)) return fail(GALS_EINVAL, "gals_advance: misaligned pointer");
     if (workspace_bytes_ < workspace_bytes(ctx))
         return fail(GALS_EINVAL, "gals_advance: workspace of %zu bytes, %zu needed", workspace_bytes_,
                     workspace_bytes(ctx));
@@ -404,6 +445,41 @@ int gals_advance(gals_ctx *ctx, void *phi, void *grad, double t0, double dt, int
     e = launch_tables(ctx, workspace, s);
     if (e == hipSuccess) e = advance_core(ctx, phi, grad, t0, dt, 0, steps, workspace, s);
     return e == hipSuccess ? GALS_OK : hip_fail(e, "gals_advance: launch");
+}
+
+int gals_advance_noalloc(gals_ctx *ctx, void *phi, void *grad, double t0, double dt,
+                         int64_t steps, void *stream)
+{
+    if (!ctx) return fail(GALS_EINVAL, "gals_advance_noalloc: NULL context");
+    if (!phi || !grad) return fail(GALS_EINVAL, "gals_advance_noalloc: NULL pointer");
+    int rc = check_advance_args(ctx, phi, grad, t0, dt, steps, "gals_advance_noalloc");
+    if (rc != GALS_OK) return rc;
+    const size_t need = workspace_bytes(ctx);
+    if (need > kScratchBytes)
+        return fail(GALS_EINVAL,
+                    "gals_advance_noalloc: the grid needs %zu bytes of scratch, the library's "
+                    "static scratch holds %zu (use gals_advance with a workspace)",
+                    need, kScratchBytes);
+    const size_t pb = size_t(ctx->g.plane) * elem_size(ctx);
+    if (overlap(phi, pb, grad, pb * size_t(ctx->dim)))
+        return fail(GALS_EINVAL, "gals_advance_noalloc: phi and grad must not overlap");
+    if (steps == 0) return GALS_OK;
+    if (ctx->device < 0)
+        return fail(GALS_EINVAL, "gals_advance_noalloc: host-only context (device -1)");
+    if (ctx->device >= kMaxScratchDevices)
+        return fail(GALS_EINVAL, "gals_advance_noalloc: device %d beyond the %d supported",
+                    ctx->device, kMaxScratchDevices);
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "gals_advance_noalloc: hipSetDevice");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gals_advance_noalloc: pending HIP error");
+    void *ws = nullptr;
+    e = scratch_address(ctx->device, &ws);
+    if (e != hipSuccess) return hip_fail(e, "gals_advance_noalloc: hipGetSymbolAddress");
+    hipStream_t s = (hipStream_t)stream;
+    e = launch_tables(ctx, ws, s);
+    if (e == hipSuccess) e = advance_core(ctx, phi, grad, t0, dt, 0, steps, ws, s);
+    return e == hipSuccess ? GALS_OK : hip_fail(e, "gals_advance_noalloc: launch");
 }
 
 int gals_eval_points(gals_ctx *ctx, const void *phi, const void *grad, const double *pts,

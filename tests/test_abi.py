@@ -426,3 +426,38 @@ def test_inflow_data_validation():
     L.gals_destroy(c3)
     L.gals_destroy(ctx)
     L.gals_destroy(c2)
+
+
+def test_noalloc_advance_validation_on_host_only_context():
+    """gals_advance_noalloc validates like gals_advance, refuses grids whose
+    workspace exceeds the library's static scratch before any HIP call, and
+    refuses host-only contexts."""
+    L = pkg.lib()
+    vp = ctypes.c_void_p
+    phi, grad = vp(0x100000), vp(0x8000000)
+    rc, ctx = _ctx(dim=2, ncell=(300, 200))
+    assert rc == pkg.OK
+    assert L.gals_advance_noalloc(ctx, phi, grad, 0.0, 0.1, 1, None) == pkg.EINVAL
+    assert b"no velocity" in L.gals_last_error()
+    assert _setvel(ctx, pkg.VORTEX, []) == pkg.OK
+    assert L.gals_advance_noalloc(ctx, None, grad, 0.0, 0.1, 1, None) == pkg.EINVAL
+    assert L.gals_advance_noalloc(ctx, phi, grad, 0.0, -0.1, 1, None) == pkg.EINVAL
+    assert L.gals_advance_noalloc(ctx, phi, grad, 0.0, 0.1, -1, None) == pkg.EINVAL
+    assert L.gals_advance_noalloc(ctx, vp(0x100002), grad, 0.0, 0.1, 1, None) == pkg.EINVAL
+    assert L.gals_advance_noalloc(ctx, phi, vp(0x100000 + 64), 0.0, 0.1, 1, None) == pkg.EINVAL
+    assert b"overlap" in L.gals_last_error()
+    assert L.gals_advance_noalloc(ctx, phi, grad, 0.0, 0.1, 0, None) == pkg.OK
+    assert L.gals_advance_noalloc(ctx, phi, grad, 0.0, 0.1, 1, None) == pkg.EINVAL
+    assert b"host-only" in L.gals_last_error()
+    L.gals_destroy(ctx)
+    # the largest square FP32 grid whose workspace fits, and one that does not
+    ws = ctypes.c_size_t()
+    for n, fits in ((2048, True), (4096, False)):
+        rc, ctx = _ctx(dim=2, ncell=(n, n))
+        assert rc == pkg.OK
+        L.gals_workspace_bytes(ctx, ctypes.byref(ws))
+        assert (ws.value <= 64 << 20) == fits
+        assert _setvel(ctx, pkg.VORTEX, []) == pkg.OK
+        assert L.gals_advance_noalloc(ctx, phi, vp(0x100000000), 0.0, 0.1, 1, None) == pkg.EINVAL
+        assert (b"static scratch" in L.gals_last_error()) == (not fits)
+        L.gals_destroy(ctx)
