@@ -32,6 +32,13 @@ tables (LeVeque's field x cos(pi t / 2.5), dt = h, to t = 2.5; a sphere and a
 cube at n = 50, 100, 150, 200, FP64) and reports the relative volume change
 beside the paper's GA-CIR rows, and the 200^3 advance's throughput.
 
+--workload table runs every configuration once and prints the per-configuration
+results (GPU rate, algorithmic HBM rate, the oracle's rate on all host threads
+and on one core, shape errors, the distance to the oracle) as one JSON line
+and, on stderr, as a markdown table: the 64^2 rotation (FP64, 128 steps), the
+2048^2 workload in FP64 and FP32, the 256^3 vector-potential workload (FP32),
+and the two bandwidth probes.
+
 --workload batched times the many-problem case instead: 512 independent
 grids of round(2^U(5,9)) cells per side, each with its own circles and
 stream function, 256 steps of dt = 2/256 per benchmark step, advanced
@@ -76,13 +83,28 @@ VARIANT_B_FLOPS_PER_NODE = ALG_FLOPS_PER_NODE - 8 + 28
 # weights 60, tricubic value and gradient 384, gradient update 18.
 FLOPS_PER_NODE_3D = 402 + 2 * 438 + 30 + 216 + 30 + 120 + 60 + 384 + 18
 BYTES_PER_NODE_3D = 32  # FP32 state: 4 planes read once + 4 planes written once
-# Bandwidth probe (rigid rotation, the cheapest field): the affine velocity
-# costs 12 flops a stage in 2D and 24 in 3D, the rest is the step as above:
-# 2D 3 x 12 + chain 80 + foot 18 + cross 8 + weights 40 + bicubic 80 + update 6;
-# 3D 3 x 24 + positions 30 + chain 216 + foot 30 + cross 120 + weights 60 +
-# tricubic 384 + update 18.
-PROBE_FLOPS_PER_NODE_2D = 3 * 12 + 80 + 18 + 8 + 40 + 80 + 6
-PROBE_FLOPS_PER_NODE_3D = 3 * 24 + 30 + 216 + 30 + 120 + 60 + 384 + 18
+# Bandwidth probe (rigid rotation, the cheapest field). The three stages of an
+# affine field compose to one affine map that the host forms once per step,
+# so a node's foot costs D^2 FP64 multiply-adds (in cell units), and its
+# Jacobian is uniform: 2D foot 8 + split 4 + cross derivatives 8 + Hermite
+# weights 40 + bicubic 80 + update 6; 3D foot 18 + split 6 + cross 120 +
+# weights 60 + tricubic 384 + update 18.
+PROBE_FLOPS_PER_NODE_2D = 8 + 4 + 8 + 40 + 80 + 6
+PROBE_FLOPS_PER_NODE_3D = 18 + 6 + 120 + 60 + 384 + 18
+
+
+# The Infinity Cache (MALL) in front of HBM: working sets below it are not HBM-bound.
+MALL_BYTES = 256 << 20
+# FP64 grid whose L1 shape error after the time-reversed run equals the FP32
+# path's at 2048^2 (measured: FP64 1.243e-9 at 1728^2, 1.116e-9 at 1792^2;
+# FP32 at 2048^2 1.237e-9).
+MATCHED_FP64_CELLS = 1728
+# The paper's only throughput figure (sec. 6.2, computational effort): the
+# superconsistent GA-CIR run of the vortex test on a 64^2 grid, 512 steps, in
+# about 9 s on one core of an unnamed desktop computer.
+PAPER_CPU_CONTEXT = {"value": 512 * 65 * 65 / 9.0, "unit": "node-updates/s", "cores": 1,
+                     "hardware": "one core of an unnamed desktop computer (the paper's, 2009)",
+                     "sample": "512 steps of 65^2 nodes in 9 s (sec. 6.2)"}
 
 
 def log(msg):
@@ -159,7 +181,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload",
                     choices=["single", "batched", "adjoint", "variants", "volume", "3d",
-                             "probe"],
+                             "probe", "table"],
                     default="single")
     ap.add_argument("--tiles", default="",
                     help="batched only: wave widths per size class, e.g. 64,0,16,64, "
@@ -167,6 +189,8 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short FP32 advance plus a plain device copy of known size "
                          "(for calibrating rocprofv3 byte counters); prints no JSON")
+    ap.add_argument("--probe-case", choices=["2d", "3d"], default="2d",
+                    help="probe workload with --profile: the case to run")
     ap.add_argument("--profile-fp64", action="store_true",
                     help="single workload with --profile: advance the FP64 state instead")
     args = ap.parse_args()
@@ -194,6 +218,8 @@ def main():
         return bench_3d(args)
     if args.workload == "probe":
         return bench_probe(args)
+    if args.workload == "table":
+        return bench_table(args)
     dev = torch.device("cuda", 0)
     w = inputs.stream_circles()
     inner = args.inner or w["steps"]
@@ -248,9 +274,9 @@ def main():
     log(f"fp32: {ms_per_step:.2f} ms/bench step, advance {adv_ms:.2f} ms, "
         f"step kernel {kernel_us:.2f} us, {value / 1e9:.2f} G node-upd/s")
 
-    # matched-error comparison: one fresh full run per precision
+    # ---------------------------------------------- full-run errors, FP32 vs FP64
     st32.copy_(ref32)
-    n32 = bench_step(g32, st32, ref32)
+    n32 = bench_step(g32, st32, ref32)  # one fresh full run
     res = {}
     if not args.no_fp64:
         g64, ref64, st64 = setup("float64")
@@ -267,24 +293,38 @@ def main():
                        "l1_shape_error": n64[2], "linf_band_error": n64[3],
                        "volume_change": n64[4] - n64[5]}
         res["l1_shape_error_ratio_fp32_over_fp64"] = n32[2] / n64[2] if n64[2] > 0 else None
+        # the FP32 final state against the FP64 one (the FP64 path matches the
+        # oracle to 1e-12), both after the whole run
+        d = state_errors(g64, st32.double(), st64, h, eps, band)
+        res["fp32_vs_fp64_final"] = d
         log(f"fp64: {res['fp64']['value'] / 1e9:.2f} G node-upd/s, L1 shape err {n64[2]:.3e}; "
-            f"fp32 L1 shape err {n32[2]:.3e}")
+            f"fp32 L1 shape err {n32[2]:.3e} (ratio {res['l1_shape_error_ratio_fp32_over_fp64']:.3f}); "
+            f"fp32 vs fp64 final: phi {d['phi']:.2e} psi {d['psi']:.2e} L1 {d['l1_shape']:.2e}")
         del g64, ref64, st64
+        res["matched_error"] = matched_error(args, w, n32[2], ms_per_step, value)
     res["fp32_l1_shape_error"] = n32[2]
     res["fp32_linf_band_error"] = n32[3]
 
     gbps = nodes * BYTES_PER_NODE / (kernel_us * 1e-6) / 1e9
     tflops = nodes * ALG_FLOPS_PER_NODE / (kernel_us * 1e-6) / 1e12
-    roofline = {"bound": "alu", "achieved": tflops, "peak": VALU_F32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": tflops / VALU_F32_PEAK_TFLOPS,
+    state_bytes = 3 * g32.plane * 4
+    roofline = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": gbps / HBM_PEAK_GBPS,
                 "traffic": traffic_record("k_step2d_f32_stream_2048.md", SINGLE_KERNEL_SOURCES),
                 "kernel": "k_step2d_stream<float, CENTRAL, taylor>",
-                "flops_per_launch": nodes * ALG_FLOPS_PER_NODE, "avg_launch_us": kernel_us,
-                "hbm_gbps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS,
-                "bytes_per_launch": nodes * BYTES_PER_NODE,
-                "packed_fp32_peak": VALU_F32_PACKED_PEAK_TFLOPS,
-                "frac_of_packed_fp32_peak": tflops / VALU_F32_PACKED_PEAK_TFLOPS}
-    achieved = gbps
+                "bytes_per_launch": nodes * BYTES_PER_NODE, "bytes_per_node": BYTES_PER_NODE,
+                "avg_launch_us": kernel_us,
+                "working_set_bytes": 2 * state_bytes,
+                "mall_resident": 2 * state_bytes < MALL_BYTES,
+                "note": "the two 50 MB state copies fit the 256 MB Infinity Cache, so these "
+                        "bytes are not all HBM traffic; the kernel is bound by its vector ALU "
+                        "(alu below), the 8192^2 probe (--workload probe) by neither",
+                "alu": {"achieved_tflops": tflops, "flops_per_node": ALG_FLOPS_PER_NODE,
+                        "flops_per_launch": nodes * ALG_FLOPS_PER_NODE,
+                        "frac_of_nonpacked_fp32_peak": tflops / VALU_F32_PEAK_TFLOPS,
+                        "nonpacked_fp32_peak_tflops": VALU_F32_PEAK_TFLOPS,
+                        "frac_of_packed_fp32_peak": tflops / VALU_F32_PACKED_PEAK_TFLOPS,
+                        "packed_fp32_peak_tflops": VALU_F32_PACKED_PEAK_TFLOPS}}
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
@@ -292,25 +332,29 @@ def main():
         import oracle
         k_cpu = 64  # about 15 s on 16 host threads
         a = time.perf_counter()
-        oracle.advance(2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
-                       w["phi0"], w["psi0"], 0.0, w["dt"], k_cpu)
+        ophi, opsi = oracle.advance(2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"],
+                                    w["period"], w["phi0"], w["psi0"], 0.0, w["dt"], k_cpu)
         b = time.perf_counter()
         cpu = {"value": nodes * k_cpu / (b - a), "unit": "node-updates/s",
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"first {k_cpu} of the {w['steps']} steps of the same 2048^2 workload "
                          f"(FP64 oracle, OpenMP), {b - a:.1f} s"}
         log(f"cpu oracle: {cpu['value'] / 1e6:.2f} M node-upd/s on {cpu['cores']} threads")
-        # and on one core: the first step
+        # and on one core: the first 4 steps
         threads = oracle.num_threads()
         oracle.set_threads(1)
+        k1 = 4
         a = time.perf_counter()
         oracle.advance(2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
-                       w["phi0"], w["psi0"], 0.0, w["dt"], 1)
+                       w["phi0"], w["psi0"], 0.0, w["dt"], k1)
         b = time.perf_counter()
         oracle.set_threads(threads)
-        cpu["single_core"] = {"value": nodes / (b - a), "unit": "node-updates/s", "cores": 1,
-                              "sample": f"the first step, {b - a:.1f} s"}
-        log(f"cpu oracle, 1 core: {nodes / (b - a) / 1e6:.3f} M node-upd/s")
+        cpu["single_core"] = {"value": nodes * k1 / (b - a), "unit": "node-updates/s",
+                              "cores": 1, "sample": f"the first {k1} steps, {b - a:.1f} s"}
+        cpu["paper_context"] = PAPER_CPU_CONTEXT
+        log(f"cpu oracle, 1 core: {nodes * k1 / (b - a) / 1e6:.3f} M node-upd/s")
+        # every GPU result of the same 64 steps against the oracle's
+        res["vs_oracle_64_steps"] = vs_oracle(w, k_cpu, ophi, opsi, h, eps, band)
 
     line = {
         "metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
@@ -321,11 +365,256 @@ def main():
                                "stream function x cos(pi t/2), 1024 steps, CFL 0.8",
                    "grid_nodes": [n + 1, n + 1], "time_steps_per_step": inner,
                    "state": "f32", "foot_coordinates": "f64", "seed": w["seed"]},
-        "hbm_gbps_algorithmic": achieved,
+        "hbm_gbps_algorithmic": gbps,
         "roofline": roofline,
         "cpu_baseline": cpu,
         **res,
     }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def state_errors(g, st, ref, h, eps, band):
+    """Normwise errors of a state against a reference state of the same FP64
+    context: phi over max|phi_ref|, psi over max|psi_ref| and over
+    max(max|psi_ref|, max|phi_ref|/h), and the L1 shape error between them."""
+    import numpy as np  # noqa: F401
+    import torch
+    out = g.norms(st, ref, eps, band)
+    grid = lambda t: g._grid_view(t)  # noqa: E731  (the valid nodes of a plane)
+    max_psi = max(float(grid(ref[1 + a]).abs().max()) for a in range(g.dim))
+    max_phi = out[7]
+    return {"phi": out[0] / max_phi, "psi": out[1] / max_psi,
+            "psi_scaled": out[1] / max(max_psi, max_phi / h), "l1_shape": out[2],
+            "linf_band": out[3], "nonfinite": out[6], "max_abs_phi_ref": max_phi,
+            "max_abs_psi_ref": max_psi}
+
+
+def vs_oracle(w, steps, ophi, opsi, h, eps, band):
+    """The FP32 and FP64 GPU states after `steps` steps against the oracle's."""
+    import numpy as np  # noqa: F401
+    import torch
+
+    import paper_0905_3409_amd as pkg
+    g64 = pkg.Grid(w["ncell"], w["lo"], w["hi"], dtype="float64")
+    oref = g64.from_numpy(ophi, opsi)
+    out = {"steps": steps}
+    for dtype in ("float32", "float64"):
+        g = pkg.Grid(w["ncell"], w["lo"], w["hi"], dtype=dtype)
+        g.set_velocity(w["kind"], w["params"], w["period"])
+        st = g.from_numpy(w["phi0"], w["psi0"])
+        g.advance(st, 0.0, w["dt"], steps)
+        torch.cuda.synchronize()
+        e = state_errors(g64, st.double(), oref, h, eps, band)
+        out["fp32" if dtype == "float32" else "fp64"] = e
+        log(f"{dtype} after {steps} steps vs oracle: phi {e['phi']:.2e} psi {e['psi']:.2e} "
+            f"(scaled {e['psi_scaled']:.2e}) L1 {e['l1_shape']:.2e}")
+        del g, st
+    return out
+
+
+def matched_error(args, w, e32, ms32, value32):
+    """FP64 throughput at the FP32 path's L1 shape error: the same physical
+    problem (circles, stream function, T = 2, CFL 0.8) on the coarser grid at
+    which the FP64 error equals the FP32 error at 2048^2, timed the same way."""
+    import numpy as np  # noqa: F401
+    import torch
+
+    import paper_0905_3409_amd as pkg
+    from paper_0905_3409_amd import inputs
+    n = MATCHED_FP64_CELLS
+    wm = inputs.stream_circles(n=n, steps=n // 2)
+    g = pkg.Grid(wm["ncell"], wm["lo"], wm["hi"], dtype="float64")
+    g.set_velocity(wm["kind"], wm["params"], wm["period"])
+    ref = g.from_numpy(wm["phi0"], wm["psi0"])
+    st = ref.clone()
+    h = 1.0 / n
+    times = []
+    for k in range(1 + max(1, min(args.steps, 3))):
+        st.copy_(ref)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        g.advance(st, 0.0, wm["dt"], wm["steps"])
+        out = g.norms(st, ref, 1.5 * h, 3 * h)  # synchronises
+        if k > 0:
+            times.append((time.perf_counter() - a) * 1e3)
+    ms = float(np.median(times))
+    nodes = (n + 1) ** 2
+    ratio = e32 / out[2]
+    r = {"fp64_cells": [n, n], "fp64_steps": wm["steps"], "fp64_l1_shape_error": out[2],
+         "fp32_l1_shape_error": e32, "ratio_fp32_over_fp64": ratio,
+         "matched": bool(1 / 1.1 <= ratio <= 1.1),
+         "fp64_ms_per_solution": ms, "fp32_ms_per_solution": ms32,
+         "fp64_node_updates_per_s": nodes * wm["steps"] / (ms * 1e-3),
+         "fp32_node_updates_per_s": value32,
+         "fp32_speedup_at_matched_error": ms / ms32,
+         "how": f"FP64 on {n}^2 cells with {wm['steps']} steps (CFL 0.8, T = 2) reaches the "
+                "L1 shape error the FP32 path reaches on 2048^2; both times are one whole "
+                "solution (advance and the shape-error reduction)"}
+    log(f"matched error: fp64 {n}^2 L1 {out[2]:.3e} vs fp32 2048^2 {e32:.3e} (ratio "
+        f"{ratio:.3f}); fp64 {ms:.1f} ms vs fp32 {ms32:.1f} ms per solution: fp32 "
+        f"{ms / ms32:.2f}x faster")
+    return r
+
+
+def _oracle_rates(dim, w, steps_all, sample_nodes=20000):
+    """The oracle's node-updates/s on all host threads (`steps_all` whole
+    steps) and on one core (a step of `sample_nodes` nodes: the whole-grid
+    cross-derivative pass plus the sampled nodes, scaled to the grid)."""
+    import numpy as np
+
+    import oracle
+    nodes = int(np.prod([c + 1 for c in w["ncell"]]))
+    a = time.perf_counter()
+    res = oracle.advance(dim, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
+                         w["phi0"], w["psi0"], 0.0, w["dt"], steps_all)
+    t_all = time.perf_counter() - a
+    threads = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        rng = np.random.default_rng(0)
+        k = min(sample_nodes, nodes)
+        pick = np.sort(rng.choice(nodes, k, replace=False))
+        args = (dim, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
+                w["phi0"], w["psi0"], 0.0, w["dt"])
+        a = time.perf_counter()
+        oracle.step_nodes(*args, np.zeros(0, dtype=np.int64))
+        t0 = time.perf_counter() - a
+        a = time.perf_counter()
+        oracle.step_nodes(*args, pick)
+        tk = time.perf_counter() - a
+    finally:
+        oracle.set_threads(threads)
+    one = nodes / (t0 + max(tk - t0, 0.0) * nodes / k)
+    return res, nodes * steps_all / t_all, threads, one
+
+
+def bench_table(args):
+    """Per-configuration results in one run (see the module docstring)."""
+    import numpy as np
+    import torch
+
+    import paper_0905_3409_amd as pkg
+    from paper_0905_3409_amd import inputs
+
+    rows = []
+
+    def gpu_run(w, dtype, steps, reps=3):
+        g = pkg.Grid(w["ncell"], w["lo"], w["hi"], dtype=dtype)
+        g.set_velocity(w["kind"], w["params"], w["period"])
+        ref = g.from_numpy(w["phi0"], w["psi0"])
+        st = ref.clone()
+        g.advance(st, 0.0, w["dt"], min(steps, 8))
+        times = []
+        for _ in range(reps):
+            st.copy_(ref)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            g.advance(st, 0.0, w["dt"], steps)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        return g, st, ref, float(np.median(times))
+
+    def row(name, prec, w, dtype, bpn, oracle_steps, full_errors=True):
+        dim = len(w["ncell"])
+        nodes = int(np.prod([c + 1 for c in w["ncell"]]))
+        h = 1.0 / w["ncell"][0]
+        g, st, ref, ms = gpu_run(w, dtype, w["steps"])
+        rate = nodes * w["steps"] / (ms * 1e-3)
+        out = g.norms(st, ref, 1.5 * h, 3 * h) if full_errors else None
+        r = {"config": name, "prec": prec, "cells": list(w["ncell"]), "steps": w["steps"],
+             "gpu_ms": ms, "gpu_node_updates_per_s": rate,
+             "hbm_gbps_algorithmic": rate * bpn / 1e9,
+             "hbm_frac": rate * bpn / 1e9 / HBM_PEAK_GBPS}
+        if out is not None:
+            r.update({"l1_shape_error": out[2], "linf_band_error": out[3]})
+        if oracle_steps and not args.no_cpu:
+            (ophi, opsi), r_all, thr, r_one = _oracle_rates(dim, w, oracle_steps)
+            r.update({"oracle_node_updates_per_s": r_all, "oracle_threads": thr,
+                      "oracle_node_updates_per_s_1core": r_one, "oracle_steps": oracle_steps})
+            g64 = pkg.Grid(w["ncell"], w["lo"], w["hi"], dtype="float64")
+            g64.set_velocity(w["kind"], w["params"], w["period"])
+            s2 = g64.from_numpy(w["phi0"], w["psi0"]) if dtype == "float64" else None
+            gg = g if dtype == "float64" else pkg.Grid(w["ncell"], w["lo"], w["hi"], dtype=dtype)
+            if dtype != "float64":
+                gg.set_velocity(w["kind"], w["params"], w["period"])
+            s1 = gg.from_numpy(w["phi0"], w["psi0"])
+            gg.advance(s1, 0.0, w["dt"], oracle_steps)
+            torch.cuda.synchronize()
+            e = state_errors(g64, s1.double(), g64.from_numpy(ophi, opsi), h, 1.5 * h, 3 * h)
+            r.update({"vs_oracle_phi": e["phi"], "vs_oracle_psi": e["psi"],
+                      "vs_oracle_psi_scaled": e["psi_scaled"]})
+            del g64, s1, s2
+        rows.append(r)
+        log(f"{name} {prec}: {rate / 1e9:.3f} G node-upd/s, {r['hbm_gbps_algorithmic']:.0f} GB/s "
+            f"algorithmic" + (f", oracle {r['oracle_node_updates_per_s'] / 1e6:.2f} M/s on "
+                             f"{r['oracle_threads']} threads, {r['oracle_node_updates_per_s_1core'] / 1e6:.3f} M/s on 1 core"
+                             if "oracle_threads" in r else ""))
+        del g, st, ref
+        torch.cuda.empty_cache()
+
+    c1 = inputs.rotation_circle()
+    row("C1 64^2 rotation", "FP64", c1, "float64", 48, c1["steps"])
+    c2 = inputs.stream_circles()
+    row("C2 2048^2 stream function", "FP64", c2, "float64", 48, 16)
+    row("C2 2048^2 stream function", "FP32", c2, "float32", BYTES_PER_NODE, 16)
+    c3 = inputs.vecpot_spheres()
+    row("C3 256^3 vector potential", "FP32", c3, "float32", BYTES_PER_NODE_3D, 1)
+    # bandwidth probes: rotation, random state (no shape error, no oracle)
+    for name, ncell, steps, bpn in (("probe 2D 8192^2 rotation", (8192, 8192), 32, BYTES_PER_NODE),
+                                    ("probe 3D 384^3 rotation", (384, 384, 384), 16,
+                                     BYTES_PER_NODE_3D)):
+        dim = len(ncell)
+        A = np.zeros((dim, dim))
+        A[0, 1], A[1, 0] = -2.0 * np.pi, 2.0 * np.pi
+        g = pkg.Grid(ncell, dtype="float32")
+        g.set_velocity(inputs.AFFINE, inputs.affine_params(np.zeros(dim), np.full(dim, 0.5), A), 0.0)
+        st = torch.zeros((1 + dim, g.plane), dtype=torch.float32, device="cuda")
+        st[0].normal_()
+        st[1:].normal_()
+        dt = 0.9 / ncell[0] / (np.pi * np.sqrt(2.0))
+        g.advance(st, 0.0, dt, 2)
+        times = []
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            g.advance(st, 0.0, dt, steps)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = float(np.median(times))
+        nodes = int(np.prod([c + 1 for c in ncell]))
+        rate = nodes * steps / (ms * 1e-3)
+        rows.append({"config": name, "prec": "FP32", "cells": list(ncell), "steps": steps,
+                     "gpu_ms": ms, "gpu_node_updates_per_s": rate,
+                     "hbm_gbps_algorithmic": rate * bpn / 1e9,
+                     "hbm_frac": rate * bpn / 1e9 / HBM_PEAK_GBPS})
+        log(f"{name}: {rate / 1e9:.3f} G node-upd/s, {rate * bpn / 1e9:.0f} GB/s algorithmic")
+        del g, st
+        torch.cuda.empty_cache()
+
+    def fmt(v, f):
+        return "-" if v is None else format(v, f)
+    log("| config | prec | GPU node-upd/s | HBM GB/s algorithmic (of 8 TB/s) | oracle node-upd/s "
+        "(threads / 1 core) | E_L1 / E_Linf band | vs oracle phi / psi (psi scaled) |")
+    log("|---|---|---|---|---|---|---|")
+    for r in rows:
+        orc = (f"{r['oracle_node_updates_per_s'] / 1e6:.2f} M ({r['oracle_threads']}) / "
+               f"{r['oracle_node_updates_per_s_1core'] / 1e6:.3f} M" if "oracle_threads" in r else "-")
+        err = (f"{r['l1_shape_error']:.3e} / {r['linf_band_error']:.3e}"
+               if "l1_shape_error" in r else "-")
+        vso = (f"{r['vs_oracle_phi']:.1e} / {r['vs_oracle_psi']:.1e} ({r['vs_oracle_psi_scaled']:.1e}) "
+               f"after {r['oracle_steps']} steps" if "vs_oracle_phi" in r else "-")
+        log(f"| {r['config']} | {r['prec']} | {r['gpu_node_updates_per_s'] / 1e9:.3f} G | "
+            f"{r['hbm_gbps_algorithmic']:.0f} ({r['hbm_frac']:.2f}) | {orc} | {err} | {vso} |")
+    line = {"metric": "per-configuration results (GPU, oracle, errors)",
+            "value": rows[2]["gpu_node_updates_per_s"], "unit": "node-updates/s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": rows[2]["gpu_ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "every configuration once (table)"},
+            "rows": rows, "roofline": None, "cpu_baseline": None,
+            "paper_context": PAPER_CPU_CONTEXT}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -734,9 +1023,9 @@ def bench_probe(args):
     table = {}
     cases = [("2d", (8192, 8192), 32, BYTES_PER_NODE, PROBE_FLOPS_PER_NODE_2D),
              ("3d", (384, 384, 384), 16, BYTES_PER_NODE_3D, PROBE_FLOPS_PER_NODE_3D)]
-    if args.profile:  # the 2D case for a few steps, then a plain copy
+    if args.profile:  # one case (--probe-case) for a few steps, then a plain copy
         cases = [(name, ncell, args.inner or 4, bpn, fpn)
-                 for name, ncell, _, bpn, fpn in cases[:1]]
+                 for name, ncell, _, bpn, fpn in cases if name == args.probe_case]
     for name, ncell, steps, bpn, fpn in cases:
         dim = len(ncell)
         A = np.zeros((dim, dim))
@@ -791,7 +1080,12 @@ def bench_probe(args):
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": main["hbm_frac"],
                      "traffic": traffic_record("k_step2d_affine_probe_8192.md",
                                                SINGLE_KERNEL_SOURCES),
-                     "kernel": "k_step2d<float, AFFINE, CENTRAL>"},
+                     "kernel": "k_step2d_affine<float, CENTRAL, superconsistent>",
+                     "bytes_per_launch": (8193 ** 2) * BYTES_PER_NODE,
+                     "avg_launch_us": main["step_us"],
+                     "alu": {"flops_per_node": PROBE_FLOPS_PER_NODE_2D,
+                             "achieved_tflops": main["tflops"],
+                             "frac_of_nonpacked_fp32_peak": main["valu_frac"]}},
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)

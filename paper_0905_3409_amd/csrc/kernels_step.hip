@@ -3,8 +3,11 @@
 // Heun's method along the characteristic).
 //
 // Each node reads only the old state (never updated in place) and writes its
-// new phi, psi with coalesced SoA stores. Departure cells are gathered through
-// the cache hierarchy, so any CFL number is handled by the same code path.
+// new phi, psi with coalesced SoA stores. The affine 2D step stages its
+// tile of the old state through LDS and gathers on-tile feet from there; the
+// other steps gather departure cells through the cache hierarchy. Feet any
+// number of cells away are gathered from global memory, so every CFL number
+// is handled.
 #include <type_traits>
 
 #include "stream2d.h"
@@ -61,6 +64,378 @@ __global__ __launch_bounds__(kBlock) void k_step2d(Geom g, Vel<T> p, Stage<T> st
     } else {
         pstore(grad_o, o, J[0] * Hx + J[2] * Hy);
         pstore(grad_o + g.plane, o, J[1] * Hx + J[3] * Hy);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS staging of the old state (used by the affine 2D step below). A block
+// owns a tile of 64 x TY nodes (four waves, each a row of 64 nodes, TY / 4
+// row groups) and stages phi, psi_x, psi_y of the tile and a halo of kHaloX
+// columns and kHaloY rows around it: the scheme's stencil is one cell, so a
+// foot less than a cell from its node (CFL < 1) reads only the node's
+// neighbours, and the cross derivative (A) one column more on each side. The
+// staging loads are coalesced and do not depend on the trace, so they are
+// issued first and their latency hides behind it. A foot whose stencil leaves
+// the staged region (CFL > 1 somewhere) gathers from global memory instead,
+// lane by lane, so any CFL number is still handled.
+// ---------------------------------------------------------------------------
+constexpr int kHaloX = 2, kHaloY = 1;
+
+template <int TY>
+struct StageTile {
+    static constexpr int W = 64 + 2 * kHaloX;  // staged columns
+    static constexpr int H = TY + 2 * kHaloY;  // staged rows
+    static constexpr int N = W * H;
+    static constexpr int PER = (N + kBlock - 1) / kBlock;  // staged values per thread
+};
+
+// The staging of one block's tile: coalesced loads of phi, psi_x, psi_y over
+// the tile and its halo into registers (issued before the foot is computed),
+// then into LDS. Thread t stages the flattened tile's entries t, t + 256, ...
+// Positions outside the grid load nothing (their offset is past the plane:
+// the buffer load returns 0) and are never read. (Staging whole rows per
+// wave, with one address add per load, cut the vector instructions by 3 % but
+// cost FP64 one wave per SIMD and measured no faster in FP32.)
+template <typename T, int TY>
+struct TileStager {
+    using S = StageTile<TY>;
+    T sv[3][S::PER];
+
+    __device__ __forceinline__ void load(const Geom &g, const T *phi, const T *gx, const T *gy,
+                                         int cx0, int ry0)
+    {
+        const Rsrc r0 = plane_rsrc(phi, g.plane), r1 = plane_rsrc(gx, g.plane),
+                   r2 = plane_rsrc(gy, g.plane);
+        const unsigned past = unsigned(g.plane);
+        const int tid = int(threadIdx.y) * 64 + int(threadIdx.x);
+#pragma unroll
+        for (int k = 0; k < S::PER; k++) {
+            const int f = tid + k * kBlock;
+            const int row = ry0 + f / S::W, col = cx0 + f % S::W;
+            const bool in = f < S::N && row >= 0 && row < g.n[1] && col >= 0 && col < g.n[0];
+            const unsigned off = in ? unsigned(row) * unsigned(g.pitch) + unsigned(col) : past;
+            sv[0][k] = bload(r0, off, T());
+            sv[1][k] = bload(r1, off, T());
+            sv[2][k] = bload(r2, off, T());
+        }
+    }
+
+    __device__ __forceinline__ void store(T (*tile)[S::N]) const
+    {
+        const int tid = int(threadIdx.y) * 64 + int(threadIdx.x);
+#pragma unroll
+        for (int k = 0; k < S::PER; k++) {
+            const int f = tid + k * kBlock;
+            if (f < S::N) {
+                tile[0][f] = sv[0][k];
+                tile[1][f] = sv[1][k];
+                tile[2][f] = sv[2][k];
+            }
+        }
+    }
+};
+
+// Tiles of 64 x TY nodes, dealt to the XCDs in contiguous bands (as
+// xcd_tile does for 64 x 4 tiles of the stream-function step).
+struct TileGrid {
+    unsigned tiles_x, tiles, magic;  // tiles per row group, in all, floor(2^32 / tiles_x)
+};
+
+// Tiles of 64 x rows nodes over the grid.
+static TileGrid tile_grid(const Geom &g, int rows)
+{
+    TileGrid tg;
+    tg.tiles_x = unsigned((g.n[0] + 63) / 64);
+    tg.tiles = tg.tiles_x * unsigned((g.n[1] + rows - 1) / rows);
+    tg.magic = tg.tiles_x > 1 ? unsigned((uint64_t(1) << 32) / tg.tiles_x) : 0xFFFFFFFFu;
+    return tg;
+}
+
+__device__ __forceinline__ bool xcd_tile_n(const TileGrid &tg, unsigned &tx, unsigned &ty)
+{
+    const unsigned per = (tg.tiles + 7u) / 8u;
+    const unsigned t = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+    unsigned r;
+    ty = udiv_magic(t, tg.tiles_x, tg.magic, r);
+    tx = r;
+    return t < tg.tiles;
+}
+
+// Row groups of four per affine tile: 64 x 8 nodes (a 64 x 4 tile stages 1.6
+// values per node and field, 64 x 8 1.3; 64 x 16 measured no faster).
+constexpr int kAffineRows = 2;
+
+// Non-temporal store of a result the next step reads only after the whole
+// launch, from a grid far larger than the caches: the line is not kept in
+// them, which leaves the L2 to the tile halos the neighbouring blocks re-read.
+template <typename T>
+__device__ __forceinline__ void pstore_nt(T *base, unsigned elem, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) +
+                                                         elem * unsigned(sizeof(T))));
+}
+
+template <typename T>
+struct AffineMap {
+    double Mc[9], kc[3];  // foot in cell units: s_a = kc_a + sum_b Mc[a][b] idx_b
+    T J[9];               // Jacobian of the foot map (J form), uniform
+    T An[9], Af[9];       // Heun: grad v at the node (t + dt) and at the foot (t)
+};
+
+template <typename T>
+static AffineMap<T> make_affine_map(const gals_ctx *ctx, double dt, double c1, double c2,
+                                    double c3)
+{
+    const int D = ctx->dim;
+    const Vel<double> &p = ctx->vd;
+    double A[9] = {0}, b[3] = {0}, xc[3] = {0};
+    for (int i = 0; i < D; i++) {
+        b[i] = p.b[i];
+        xc[i] = p.c[i];
+        for (int j = 0; j < D; j++) A[i * 3 + j] = p.A[i * 3 + j];
+    }
+    auto mm = [&](const double *X, const double *Y, double *Z) {  // Z = X Y (3x3)
+        double t[9];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; k++) acc += X[i * 3 + k] * Y[k * 3 + j];
+                t[i * 3 + j] = acc;
+            }
+        for (int k = 0; k < 9; k++) Z[k] = t[k];
+    };
+    auto mv = [&](const double *X, const double *y, double *z) {
+        double t[3];
+        for (int i = 0; i < 3; i++) t[i] = X[i * 3] * y[0] + X[i * 3 + 1] * y[1] + X[i * 3 + 2] * y[2];
+        for (int i = 0; i < 3; i++) z[i] = t[i];
+    };
+    double V0[9], V1[9], V2[9], P[9], w0[3], w1[3], w2[3], q[3];
+    for (int k = 0; k < 9; k++) V0[k] = c1 * A[k];
+    for (int i = 0; i < 3; i++) w0[i] = c1 * b[i];
+    for (int k = 0; k < 9; k++) P[k] = double(k % 4 == 0) - dt * V0[k];  // I - dt V0
+    mm(A, P, V1);
+    for (int k = 0; k < 9; k++) V1[k] *= c2;
+    mv(A, w0, q);
+    for (int i = 0; i < 3; i++) w1[i] = c2 * (b[i] - dt * q[i]);
+    for (int k = 0; k < 9; k++) P[k] = double(k % 4 == 0) - dt * 0.25 * (V0[k] + V1[k]);
+    mm(A, P, V2);
+    for (int k = 0; k < 9; k++) V2[k] *= c3;
+    double s01[3];
+    for (int i = 0; i < 3; i++) s01[i] = w0[i] + w1[i];
+    mv(A, s01, q);
+    for (int i = 0; i < 3; i++) w2[i] = c3 * (b[i] - dt * 0.25 * q[i]);
+    double M[9], m[3];
+    for (int k = 0; k < 9; k++)
+        M[k] = double(k % 4 == 0) - dt * (V0[k] * (1.0 / 6.0) + V1[k] * (1.0 / 6.0) + V2[k] * (2.0 / 3.0));
+    for (int i = 0; i < 3; i++)
+        m[i] = -dt * (w0[i] * (1.0 / 6.0) + w1[i] * (1.0 / 6.0) + w2[i] * (2.0 / 3.0));
+    // cell units: s_a = (foot_a - lo_a) / h_a with node x_b = lo_b + idx_b h_b
+    AffineMap<T> am;
+    for (int a = 0; a < 3; a++) {
+        am.kc[a] = 0.0;
+        for (int j = 0; j < 3; j++) am.Mc[a * 3 + j] = 0.0;
+    }
+    const Geom &g = ctx->g;
+    for (int a = 0; a < D; a++) {
+        double k = (xc[a] - g.lo[a]) + m[a];
+        for (int j = 0; j < D; j++) {
+            am.Mc[a * 3 + j] = M[a * 3 + j] * g.h[j] / g.h[a];
+            k += M[a * 3 + j] * (g.lo[j] - xc[j]);
+        }
+        am.kc[a] = k / g.h[a];
+    }
+    for (int i = 0; i < D; i++)
+        for (int j = 0; j < D; j++) {
+            am.J[i * D + j] = T(M[i * 3 + j]);
+            am.An[i * D + j] = T(c1 * A[i * 3 + j]);
+            am.Af[i * D + j] = T(c2 * A[i * 3 + j]);
+        }
+    return am;
+}
+
+// Boundary treatment and split of a foot given in cell units: outside only
+// beyond kFootTol cells (then projected: local coordinate 0 or 1 and the
+// normal derivative dropped), cell index clamped to [0, nc - 1], local
+// coordinate unclamped otherwise (the same rules as project_foot + split).
+template <typename T, int D>
+__device__ __forceinline__ void split_cells(const Geom &g, const double *s, int *cell, T *xi,
+                                            bool *outb)
+{
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        const bool below = s[a] < g.lowc[a], above = s[a] > g.outc[a];
+        const double fl = fmin(fmax(floor(s[a]), 0.0), g.lastc[a]);
+        cell[a] = int(fl);
+        T x = T(s[a] - fl);
+        x = below ? T(0) : x;
+        xi[a] = above ? T(1) : x;
+        outb[a] = below || above;
+    }
+}
+
+// Cell data from the staged tile at index b of the cell's lower-left node:
+// every neighbour sits at a fixed offset (one row = W). The central cross
+// derivative reads one column beyond each side of the cell; at the first and
+// last cell of a row that column lies outside the grid, and the one-sided
+// differences used there do not read it (same values as gather2d).
+template <typename T, int MIX, int W>
+__device__ __forceinline__ void gather2d_lds(const Geom &g, const T *t0, const T *t1,
+                                             const T *t2, int b, int cx, T d[4][4])
+{
+    d[0][0] = t0[b]; d[1][0] = t0[b + 1]; d[2][0] = t0[b + W]; d[3][0] = t0[b + W + 1];
+    d[0][1] = t1[b]; d[1][1] = t1[b + 1]; d[2][1] = t1[b + W]; d[3][1] = t1[b + W + 1];
+    if constexpr (MIX == GALS_MIXED_CENTRAL) {
+        const T u0[4] = {t2[b - 1], t2[b], t2[b + 1], t2[b + 2]};
+        const T u1[4] = {t2[b + W - 1], t2[b + W], t2[b + W + 1], t2[b + W + 2]};
+        d[0][2] = u0[1]; d[1][2] = u0[2];
+        d[2][2] = u1[1]; d[3][2] = u1[2];
+        const T inv2h = geo_i2h<T>(g, 0);
+        const bool lo = cx == 0, hi = cx + 1 == g.nc[0];
+        diff_pair<T, sizeof(T) == 4>(u0, lo, hi, inv2h, d[0][3], d[1][3]);
+        diff_pair<T, sizeof(T) == 4>(u1, lo, hi, inv2h, d[2][3], d[3][3]);
+    } else {
+        d[0][2] = t2[b]; d[1][2] = t2[b + 1]; d[2][2] = t2[b + W]; d[3][2] = t2[b + W + 1];
+        if constexpr (MIX == GALS_MIXED_CELL) {
+            T ga[4], gb[4], out[4];
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                ga[v] = d[v][1];
+                gb[v] = d[v][2];
+            }
+            cell_cross(ga, gb, geo_ih<T>(g, 0), geo_ih<T>(g, 1), out);
+#pragma unroll
+            for (int v = 0; v < 4; v++) d[v][3] = out[v];
+        } else {
+            d[0][3] = d[1][3] = d[2][3] = d[3][3] = T(0);
+        }
+    }
+}
+
+// 2D step for an affine field: the foot from the host's map, the old state
+// staged in a 64 x 4R node tile with its halo, the gather
+// from the tile at fixed offsets, or from global memory for a stencil off
+// the tile.
+template <typename T, int MIX, int PSI, int R>
+__global__ __launch_bounds__(kBlock) void k_step2d_affine(Geom g, TileGrid tg, AffineMap<T> am,
+                                                          double dt, const T *__restrict__ phi,
+                                                          const T *__restrict__ grad,
+                                                          T *__restrict__ phi_o,
+                                                          T *__restrict__ grad_o)
+{
+    using S = StageTile<4 * R>;
+    __shared__ T tile[3][S::N];
+    unsigned tx, ty;
+    if (!xcd_tile_n(tg, tx, ty)) return;  // whole blocks only: before the barrier
+    const int cx0 = int(tx) * 64 - kHaloX, ry0 = int(ty) * (4 * R) - kHaloY;
+    const T *gx = grad, *gy = grad + g.plane;
+    TileStager<T, 4 * R> stager;
+    stager.load(g, phi, gx, gy, cx0, ry0);
+    const int i = int(tx) * 64 + int(threadIdx.x);
+    int cell[R][2];
+    T xi[R][2];
+    bool outb[R][2];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int j = __builtin_amdgcn_readfirstlane(ry0 + kHaloY + int(threadIdx.y) + 4 * r);
+        double sc[2];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+            sc[a] = am.kc[a] + am.Mc[a * 3] * double(i) + am.Mc[a * 3 + 1] * double(j);
+        split_cells<T, 2>(g, sc, cell[r], xi[r], outb[r]);
+    }
+    stager.store(tile);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int j = __builtin_amdgcn_readfirstlane(ry0 + kHaloY + int(threadIdx.y) + 4 * r);
+        const int cx = cell[r][0], cy = cell[r][1];
+        const bool on = cx - 1 >= cx0 && cx + 2 < cx0 + S::W && cy >= ry0 && cy + 1 < ry0 + S::H;
+        T d[4][4];
+        gather2d_lds<T, MIX, S::W>(g, tile[0], tile[1], tile[2],
+                                   on ? (cy - ry0) * S::W + (cx - cx0) : S::W + 1, cx, d);
+        if (!on)
+            gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane),
+                             plane_rsrc(gy, g.plane), cx, cy, d);
+        Basis<T> bx, by;
+        basis<T, false>(xi[r][0], geo_h<T>(g, 0), geo_ih<T>(g, 0), bx);
+        basis<T, false>(xi[r][1], geo_h<T>(g, 1), geo_ih<T>(g, 1), by);
+        T H, Hx, Hy;
+        hermite2d(d, bx, by, H, Hx, Hy);
+        if (outb[r][0]) Hx = T(0);
+        if (outb[r][1]) Hy = T(0);
+        if (i >= g.n[0] || j >= g.n[1]) continue;
+        const unsigned o = unsigned(j) * unsigned(g.pitch) + unsigned(i);
+        T g0, g1;
+        if constexpr (PSI == GALS_PSI_HEUN) {
+            T ps[2];
+            const T gH[2] = {Hx, Hy};
+            heun_gradient<T, 2>(am.Af, am.An, T(dt), gH, ps);
+            g0 = ps[0];
+            g1 = ps[1];
+        } else {
+            g0 = am.J[0] * Hx + am.J[2] * Hy;
+            g1 = am.J[1] * Hx + am.J[3] * Hy;
+        }
+        pstore_nt(phi_o, o, H);
+        pstore_nt(grad_o, o, g0);
+        pstore_nt(grad_o + g.plane, o, g1);
+    }
+}
+
+// 3D step for an affine field: the foot from the host's map, one thread per
+// node, the 64-value gather through the caches.
+template <typename T, int MIX, int PSI>
+__global__ __launch_bounds__(kBlock) void k_step3d_affine(Geom g, AffineMap<T> am, double dt,
+                                                          const T *__restrict__ phi,
+                                                          const T *__restrict__ grad,
+                                                          T *__restrict__ phi_o,
+                                                          T *__restrict__ grad_o)
+{
+    unsigned blk;
+    if (!xcd_block(unsigned((g.nodes + kBlock - 1) / kBlock), blk)) return;
+    const unsigned id = blk * kBlock + threadIdx.x;
+    if (id >= unsigned(g.nodes)) return;
+    unsigned ri, rj;
+    const unsigned row = udiv_magic(id, unsigned(g.n[0]), g.n_magic[0], ri);
+    const int k = int(udiv_magic(row, unsigned(g.n[1]), g.n_magic[1], rj));
+    const int i = int(ri), j = int(rj);
+    double sc[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+        sc[a] = am.kc[a] + am.Mc[a * 3] * double(i) + am.Mc[a * 3 + 1] * double(j) +
+                am.Mc[a * 3 + 2] * double(k);
+    int cell[3];
+    T xi[3];
+    bool outb[3];
+    split_cells<T, 3>(g, sc, cell, xi, outb);
+    const T *gx = grad, *gy = grad + g.plane, *gz = grad + 2 * g.plane;
+    T d[8][8];
+    gather3d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane), plane_rsrc(gy, g.plane),
+                     plane_rsrc(gz, g.plane), cell[0], cell[1], cell[2], d);
+    Basis<T> bx, by, bz;
+    basis<T, false>(xi[0], geo_h<T>(g, 0), geo_ih<T>(g, 0), bx);
+    basis<T, false>(xi[1], geo_h<T>(g, 1), geo_ih<T>(g, 1), by);
+    basis<T, false>(xi[2], geo_h<T>(g, 2), geo_ih<T>(g, 2), bz);
+    T H, Hx, Hy, Hz;
+    hermite3d(d, bx, by, bz, H, Hx, Hy, Hz);
+    if (outb[0]) Hx = T(0);
+    if (outb[1]) Hy = T(0);
+    if (outb[2]) Hz = T(0);
+    const unsigned o = (unsigned(k) * unsigned(g.n[1]) + unsigned(j)) * unsigned(g.pitch) +
+                       unsigned(i);
+    pstore(phi_o, o, H);
+    if constexpr (PSI == GALS_PSI_HEUN) {
+        T ps[3];
+        const T gH[3] = {Hx, Hy, Hz};
+        heun_gradient<T, 3>(am.Af, am.An, T(dt), gH, ps);
+        pstore(grad_o, o, ps[0]);
+        pstore(grad_o + g.plane, o, ps[1]);
+        pstore(grad_o + 2 * g.plane, o, ps[2]);
+    } else {
+        const T *J = am.J;
+        pstore(grad_o, o, J[0] * Hx + J[3] * Hy + J[6] * Hz);
+        pstore(grad_o + g.plane, o, J[1] * Hx + J[4] * Hy + J[7] * Hz);
+        pstore(grad_o + 2 * g.plane, o, J[2] * Hx + J[5] * Hy + J[8] * Hz);
     }
 }
 
@@ -290,7 +665,12 @@ __global__ __launch_bounds__(kBlock) void k_stream_tables(Geom g, Vel<double> p,
 
 // GA-CIR step for the sine stream-function field. Launch: blocks of 64 x 4
 // threads over 64 x 4 node tiles; each wave owns 64 consecutive nodes of one
-// row, so the row table is read once per wave through scalar loads.
+// row, so the row table is read once per wave through scalar loads. The cell
+// data are gathered through the caches after the trace: the kernel is bound
+// by its vector ALU, and staging the tile through LDS (as the affine step
+// does) measured slower in both precisions (FP32 34.0 -> 39.9 us, FP64 87.2
+// -> 102.4 us per 2049^2 step: more instructions, and in FP64 one wave per
+// SIMD fewer).
 template <typename T, int MIX, bool TAYLOR, int PSI>
 __global__ __launch_bounds__(kBlock) void k_step2d_stream(
     Geom g, Vel<T> p, Stage<T> st, double dt, const T *__restrict__ coltab,
@@ -303,8 +683,8 @@ __global__ __launch_bounds__(kBlock) void k_step2d_stream(
     const int j = __builtin_amdgcn_readfirstlane(int(ty) * 4 + int(threadIdx.y));
     if (j >= g.n[1] || i >= g.n[0]) return;
     stream_node<T, MIX, TAYLOR, PSI>(g, p, st, dt, coltab + int64_t(i) * kJet,
-                                rowtab + int64_t(j) * kJet, phi, grad, grad + g.plane,
-                                phi_o, grad_o, grad_o + g.plane, i, j);
+                                     rowtab + int64_t(j) * kJet, phi, grad, grad + g.plane,
+                                     phi_o, grad_o, grad_o + g.plane, i, j);
 }
 
 hipError_t launch_stream_tables(const gals_ctx *ctx, void *coltab, void *rowtab, hipStream_t s)
@@ -368,17 +748,31 @@ static hipError_t launch_typed(const gals_ctx *ctx, const Vel<T> &p, const void 
     const Stage<T> st = make_stage<T>(dt, c1, c2, c3);
     // rounded up to a multiple of 8 for the XCD band mapping (xcd_block)
     const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock + 7) / 8u * 8u;
+    if constexpr (KIND == GALS_VEL_AFFINE) {
+        const AffineMap<T> am = make_affine_map<T>(ctx, dt, c1, c2, c3);
+        if (ctx->dim == 2) {
+            const TileGrid tg = tile_grid(ctx->g, 4 * kAffineRows);
+            hipLaunchKernelGGL((k_step2d_affine<T, MIX, PSI, kAffineRows>),
+                               dim3((tg.tiles + 7u) / 8u * 8u),
+                               dim3(64, 4), 0, s, ctx->g, tg, am, dt, (const T *)phi,
+                               (const T *)grad, (T *)phi_o, (T *)grad_o);
+        } else {
+            hipLaunchKernelGGL((k_step3d_affine<T, MIX, PSI>), dim3(blocks), dim3(kBlock), 0, s,
+                               ctx->g, am, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
+                               (T *)grad_o);
+        }
+        return hipGetLastError();
+    }
     if (ctx->dim == 2) {
-        if constexpr (KIND == GALS_VEL_AFFINE || KIND == GALS_VEL_STREAM_SIN ||
-                      KIND == GALS_VEL_VORTEX || KIND == GALS_VEL_PSEUDO1D) {
+        if constexpr (KIND == GALS_VEL_STREAM_SIN || KIND == GALS_VEL_VORTEX ||
+                      KIND == GALS_VEL_PSEUDO1D) {
             hipLaunchKernelGGL((k_step2d<T, KIND, MIX, PSI>), dim3(blocks), dim3(kBlock), 0, s,
                                ctx->g, p, st, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
                                (T *)grad_o);
             return hipGetLastError();
         }
     } else {
-        if constexpr (KIND == GALS_VEL_AFFINE || KIND == GALS_VEL_VECPOT_SIN ||
-                      KIND == GALS_VEL_LEVEQUE3D) {
+        if constexpr (KIND == GALS_VEL_VECPOT_SIN || KIND == GALS_VEL_LEVEQUE3D) {
             hipLaunchKernelGGL((k_step3d<T, KIND, MIX, PSI>), dim3(blocks), dim3(kBlock), 0, s,
                                ctx->g, p, st, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
                                (T *)grad_o);

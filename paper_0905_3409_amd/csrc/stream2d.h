@@ -250,25 +250,18 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
     }
 }
 
-// One GA-CIR step at node (i, j) of a grid with a sine stream-function field:
-// the trace, the gather and the bicubic update (superconsistent, or Heun's
-// method with grad v at the foot from the node's jet).
-template <typename T, int MIX, bool TAYLOR, int PSI = GALS_PSI_SUPERCONSISTENT, class P>
-__device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Stage<T> &st,
-                                            double dt, const T *__restrict__ U,
-                                            const T *__restrict__ Y,
-                                            const T *__restrict__ phi, const T *__restrict__ gx,
-                                            const T *__restrict__ gy, T *__restrict__ phi_o,
-                                            T *__restrict__ gx_o, T *__restrict__ gy_o, int i,
-                                            int j)
+// The part of a stream-function step after the trace and the gather: the
+// bicubic, the boundary treatment of its gradient, and the update
+// (superconsistent, or Heun's method with grad v at the foot from the node's
+// jet) into the output planes.
+template <typename T, bool TAYLOR, int PSI, class P>
+__device__ __forceinline__ void stream_finish(const Geom &g, const P &p, const Stage<T> &st,
+                                              double dt, const T *__restrict__ U,
+                                              const T *__restrict__ Y, const StreamFoot<T> &f,
+                                              const T (&d)[4][4], T *__restrict__ phi_o,
+                                              T *__restrict__ gx_o, T *__restrict__ gy_o, int i,
+                                              int j)
 {
-    StreamFoot<T> f;
-    stream_trace<T, TAYLOR, PSI == GALS_PSI_SUPERCONSISTENT>(g, p, st, dt, U, Y, i, j, f);
-    T d[4][4];
-    // buffer resources made here, not before the trace, so that they are not
-    // held in scalar registers across it
-    gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane),
-                     plane_rsrc(gy, g.plane), f.cell[0], f.cell[1], d);
     Basis<T> bx, by;
     basis<T, false>(T(f.xi[0]), geo_h<T>(g, 0), geo_ih<T>(g, 0), bx);
     basis<T, false>(T(f.xi[1]), geo_h<T>(g, 1), geo_ih<T>(g, 1), by);
@@ -294,6 +287,27 @@ __device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Sta
         pstore(gx_o, o, f.J[0] * Hx + f.J[2] * Hy);
         pstore(gy_o, o, f.J[1] * Hx + f.J[3] * Hy);
     }
+}
+
+// One GA-CIR step at node (i, j) of a grid with a sine stream-function field:
+// the trace, the gather from global memory and the bicubic update.
+template <typename T, int MIX, bool TAYLOR, int PSI = GALS_PSI_SUPERCONSISTENT, class P>
+__device__ __forceinline__ void stream_node(const Geom &g, const P &p, const Stage<T> &st,
+                                            double dt, const T *__restrict__ U,
+                                            const T *__restrict__ Y,
+                                            const T *__restrict__ phi, const T *__restrict__ gx,
+                                            const T *__restrict__ gy, T *__restrict__ phi_o,
+                                            T *__restrict__ gx_o, T *__restrict__ gy_o, int i,
+                                            int j)
+{
+    StreamFoot<T> f;
+    stream_trace<T, TAYLOR, PSI == GALS_PSI_SUPERCONSISTENT>(g, p, st, dt, U, Y, i, j, f);
+    T d[4][4];
+    // buffer resources made here, not before the trace, so that they are not
+    // held in scalar registers across it
+    gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane),
+                     plane_rsrc(gy, g.plane), f.cell[0], f.cell[1], d);
+    stream_finish<T, TAYLOR, PSI>(g, p, st, dt, U, Y, f, d, phi_o, gx_o, gy_o, i, j);
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin by id, and each XCD has its
