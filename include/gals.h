@@ -307,7 +307,9 @@ typedef struct gals_batch gals_batch;
  * on [lo[2p], hi[2p]] x [lo[2p+1], hi[2p+1]], each plane under 2 GiB.
  * device -1: host-only (layout and validation). The batch owns small device
  * tables (problem descriptors and the tile list) that it uploads before its
- * first advance; EINVAL for invalid sizes, ENOMEM when out of host memory. */
+ * first advance; EINVAL for invalid sizes, ENOMEM when out of host memory.
+ * Its wave shapes start as those recorded for its shape by
+ * gals_batch_autotune (see there), else 64 for every class. */
 int gals_batch_create(gals_batch **out, int64_t nprob, const int64_t *ncell, const double *lo,
                       const double *hi, int prec, int mixed_mode, int bc, int device);
 int gals_batch_destroy(gals_batch *b);
@@ -334,7 +336,13 @@ int gals_batch_advance(gals_batch *b, void *state, double t0, double dt, int64_t
 /* Choose the wave shape per size class by timing `steps` steps of each
  * candidate on this batch (coordinate descent over the classes); keeps the
  * fastest and returns its time in *best_ms. Advances `state` while timing:
- * pass a scratch copy. Synchronises the stream. */
+ * pass a scratch copy. Synchronises the stream. The choice is recorded for
+ * the batch's shape (precision, cross-derivative rule and every problem's
+ * cell counts, in order): a batch of the same shape created later in the
+ * process starts with it, and when the environment variable GALS_TUNE_FILE
+ * names a file the choice is appended to it as a line "key w0 w1 w2 w3" (key
+ * in hex), which gals_batch_create of later processes reads (the last line
+ * for a key wins; unreadable or invalid lines are ignored). */
 int gals_batch_autotune(gals_batch *b, void *state, double dt, int64_t steps, void *workspace,
                         size_t workspace_bytes, void *stream, double *best_ms);
 

@@ -7,6 +7,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <stdlib.h>
+
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -38,6 +42,79 @@ const unsigned kShapes[4] = {64u, 32u, 16u, 0u};
 // Grid-size class of a problem by nodes per row.
 int size_class(int n0) { return n0 <= 48 ? 0 : n0 <= 96 ? 1 : n0 <= 192 ? 2 : 3; }
 
+// ---------------------------------------------------------------------------
+// Tuned wave shapes per batch shape. The key is a 64-bit FNV-1a hash of the
+// precision, the cross-derivative rule and every problem's cell counts in
+// order; gals_batch_autotune records its choice under it, in this process
+// and, when the environment variable GALS_TUNE_FILE names a file, as one
+// line "key w0 w1 w2 w3" appended to that file; gals_batch_create starts a
+// batch of a recorded shape with the recorded shapes (the file's last line
+// for the key wins over earlier ones, the process's own record over the
+// file).
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mutex;
+std::map<uint64_t, std::vector<unsigned>> g_tuned;
+
+uint64_t fnv1a(uint64_t h, uint64_t v)
+{
+    for (int k = 0; k < 8; k++) {
+        h ^= (v >> (8 * k)) & 0xffu;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+uint64_t shape_key(int prec, int mixed, int64_t nprob, const int64_t *ncell)
+{
+    uint64_t h = 14695981039346656037ull;
+    h = fnv1a(h, uint64_t(prec));
+    h = fnv1a(h, uint64_t(mixed));
+    h = fnv1a(h, uint64_t(nprob));
+    for (int64_t k = 0; k < 2 * nprob; k++) h = fnv1a(h, uint64_t(ncell[k]));
+    return h;
+}
+
+bool valid_shape(unsigned w) { return w == 64u || w == 32u || w == 16u || w == 0u; }
+
+// The recorded shapes for `key`, if any (the process's record first).
+bool lookup_tuned(uint64_t key, unsigned out[4])
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+        for (int c = 0; c < 4; c++) out[c] = it->second[c];
+        return true;
+    }
+    const char *path = getenv("GALS_TUNE_FILE");
+    if (!path || !*path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    unsigned long long k;
+    unsigned w[4];
+    while (fscanf(f, "%llx %u %u %u %u", &k, &w[0], &w[1], &w[2], &w[3]) == 5) {
+        if (uint64_t(k) != key) continue;
+        if (!(valid_shape(w[0]) && valid_shape(w[1]) && valid_shape(w[2]) && valid_shape(w[3])))
+            continue;
+        for (int c = 0; c < 4; c++) out[c] = w[c];
+        found = true;
+    }
+    fclose(f);
+    return found;
+}
+
+void record_tuned(uint64_t key, const unsigned w[4])
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tuned[key] = std::vector<unsigned>(w, w + 4);
+    const char *path = getenv("GALS_TUNE_FILE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%016llx %u %u %u %u\n", (unsigned long long)key, w[0], w[1], w[2], w[3]);
+    fclose(f);
+}
+
 }  // namespace
 
 struct gals_batch {
@@ -51,6 +128,7 @@ struct gals_batch {
     int64_t total_elems = 0, tab_elems = 0;
     int max_entries = 0;
     unsigned class_wx[4] = {64u, 64u, 64u, 64u};
+    uint64_t shape_key = 0;  // key of the batch's shape for the tuning record
     unsigned blocks = 0;
     // device copies of the problem descriptors and the tile list
     void *d_probs = nullptr;
@@ -327,6 +405,10 @@ int gals_batch_create(gals_batch **out, int64_t nprob, const int64_t *ncell, con
     } else {
         b->blocks = 2048;
     }
+    b->shape_key = shape_key(prec, mixed_mode, nprob, ncell);
+    unsigned tuned[4];
+    if (lookup_tuned(b->shape_key, tuned))
+        for (int c = 0; c < 4; c++) b->class_wx[c] = tuned[c];
     *out = b;
     return GALS_OK;
 }
@@ -511,6 +593,7 @@ int gals_batch_autotune(gals_batch *b, void *state, double dt, int64_t steps, vo
     if (rc == GALS_OK) rc = upload(b);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (rc == GALS_OK) record_tuned(b->shape_key, b->class_wx);
     if (rc == GALS_OK && best_ms) *best_ms = double(best);
     return rc;
 }

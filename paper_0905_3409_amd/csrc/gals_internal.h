@@ -17,8 +17,13 @@ constexpr int kRedSlots = 8;         // doubles per partial
 constexpr int kJetTaylor = 20;       // stream-function jet entries per column / row
 constexpr int kJet = 24;             // table stride: the jet, sin and cos of pi x, 2 unused
 // Taylor evaluation of the FP32 stream-function velocity at a stage point is
-// used while kx |dx| + ky |dy| stays below this bound (truncation < FP32 rounding)
+// used while kx |dx| + ky |dy| stays below kTaylorMax (truncation < FP32
+// rounding), and below kTaylorMax2 a degree lower: velocity degree 2 and its
+// Jacobian degree 1, whose dropped terms are (k d)^3 / 6 = 1.5e-8 of the
+// velocity and, through dt grad v <= k d, (k d)^3 / 2 = 4.6e-8 in the
+// superconsistent Jacobian (at most one FP32 ulp).
 constexpr float kTaylorMax = 0.03f;
+constexpr float kTaylorMax2 = 0.0045f;
 
 // A foot counts as outside the domain only when it lies more than kFootTol
 // cells beyond the boundary (see project_foot).

@@ -80,8 +80,10 @@ struct StreamJet {
     T d10, d01, d20, d11, d02, d30, d21, d12, d03, d40, d31, d22, d13, d04;
 };
 
+// Orders 1..3 of the jet (u, y: a node's column and row table entries of
+// orders 0..3), and order 4 (entries of orders 0..4).
 template <typename T>
-__device__ __forceinline__ void stream_jet(const T *u, const T *y, StreamJet<T> &J)
+__device__ __forceinline__ void stream_jet3(const T *u, const T *y, StreamJet<T> &J)
 {
     J.d10 = dot4(u + 4, y);
     J.d01 = dot4(u, y + 4);
@@ -92,11 +94,31 @@ __device__ __forceinline__ void stream_jet(const T *u, const T *y, StreamJet<T> 
     J.d21 = dot4(u + 8, y + 4);
     J.d12 = dot4(u + 4, y + 8);
     J.d03 = dot4(u, y + 12);
+}
+
+template <typename T>
+__device__ __forceinline__ void stream_jet4(const T *u, const T *y, StreamJet<T> &J)
+{
     J.d40 = dot4(u + 16, y);
     J.d31 = dot4(u + 12, y + 4);
     J.d22 = dot4(u + 8, y + 8);
     J.d13 = dot4(u + 4, y + 12);
     J.d04 = dot4(u, y + 16);
+}
+
+// (s_x, s_y) to degree 2 and (s_xx, s_xy, s_yy) to degree 1 at offset
+// (dx, dy): only the jet of order 3 enters. Used while kx |dx| + ky |dy| <=
+// kTaylorMax2, where the dropped terms stay below FP32 rounding.
+template <typename T>
+__device__ __forceinline__ void stream_taylor2(const StreamJet<T> &J, T dx, T dy, T &sx, T &sy,
+                                               T &sxx, T &sxy, T &syy)
+{
+    const T hx = T(0.5) * dx, hy = T(0.5) * dy;
+    sx = J.d10 + dx * (J.d20 + hx * J.d30 + dy * J.d21) + dy * (J.d11 + hy * J.d12);
+    sy = J.d01 + dx * (J.d11 + hx * J.d21 + dy * J.d12) + dy * (J.d02 + hy * J.d03);
+    sxx = J.d20 + dx * J.d30 + dy * J.d21;
+    sxy = J.d11 + dx * J.d21 + dy * J.d12;
+    syy = J.d02 + dx * J.d12 + dy * J.d03;
 }
 
 // (s_x, s_y, s_xx, s_xy, s_yy) at offset (dx, dy) from the node, each
@@ -138,14 +160,11 @@ __device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J,
         stream_taylor(J, dx, dy, sx, sy, sxx, sxy, syy);
         from_stream(sx, sy, sxx, sxy, syy, T(1), v, A);
     } else {
-        T sx[4], cx[4], sy[4], cy[4];
+        T s1x, c1x, s1y, c1y;  // sin and cos of pi x and pi y at the stage point
         constexpr T dmax = T(kShiftMaxLong<T> / kPi);
         if (fabs(dx) <= dmax && fabs(dy) <= dmax) {
-            T s, cs;
-            shifted_sincos_long(U[kJetTaylor], U[kJetTaylor + 1], dx, s, cs);
-            multiples_from(s, cs, sx, cx);
-            shifted_sincos_long(Y[kJetTaylor], Y[kJetTaylor + 1], dy, s, cs);
-            multiples_from(s, cs, sy, cy);
+            shifted_sincos_long(U[kJetTaylor], U[kJetTaylor + 1], dx, s1x, c1x);
+            shifted_sincos_long(Y[kJetTaylor], Y[kJetTaylor + 1], dy, s1y, c1y);
         } else {
             // FP32 forms the node's coordinates only here, off the common path
             // (x0, y0 unused); FP64 passes them in (forming them here would
@@ -154,10 +173,10 @@ __device__ __forceinline__ void stream_stage(const P &p, const StreamJet<T> &J,
                 x0 = node_coord(g.lo[0], i, g.h[0]);
                 y0 = node_coord(g.lo[1], j, g.h[1]);
             }
-            sincos_multiples(T(x0 + double(dx)), sx, cx);
-            sincos_multiples(T(y0 + double(dy)), sy, cy);
+            sincospi_t(T(x0 + double(dx)), &s1x, &c1x);
+            sincospi_t(T(y0 + double(dy)), &s1y, &c1y);
         }
-        stream_modes(p, sx, cx, sy, cy, T(1), v, A);
+        stream_modes_from(p, s1x, c1x, s1y, c1y, T(1), v, A);
     }
 }
 
@@ -187,14 +206,25 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
 {
     StreamJet<T> &jet = f.jet;
     {
+        T y[16], u[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            y[k] = Y[k];
+            u[k] = U[k];
+        }
+        stream_jet3(u, y, jet);
+    }
+    jet.d40 = jet.d31 = jet.d22 = jet.d13 = jet.d04 = T(0);
+    // the order-4 jet, for the lanes whose stages need it
+    auto order4 = [&]() {
         T y[kJetTaylor], u[kJetTaylor];
 #pragma unroll
         for (int k = 0; k < kJetTaylor; k++) {
             y[k] = Y[k];
             u[k] = U[k];
         }
-        stream_jet(u, y, jet);
-    }
+        stream_jet4(u, y, jet);
+    };
     const double x0 = sizeof(T) == 8 ? node_coord(g.lo[0], i, g.h[0]) : 0.0;
     const double y0 = sizeof(T) == 8 ? node_coord(g.lo[1], j, g.h[1]) : 0.0;
     // w_k, R_k: velocity and velocity Jacobian at stage k without the time
@@ -202,14 +232,32 @@ __device__ __forceinline__ void stream_trace(const Geom &g, const P &p, const St
     T w0[2], R0[4], w1[2], R1[4], w2[2], R2[4];
     // stage 1 at the node, time t + dt
     from_stream(jet.d10, jet.d01, jet.d20, jet.d11, jet.d02, T(1), w0, R0);
-    // stage 2 at x1 = x - dt v0, time t
+    // stage 2 at x1 = x - dt v0, time t; a lane whose stage offsets are tiny
+    // takes the degree-2 polynomial from the order-3 jet, the others the
+    // order-4 jet and stream_stage
     f.d1[0] = -st.e1 * w0[0];
     f.d1[1] = -st.e1 * w0[1];
-    stream_stage<T, TAYLOR>(p, jet, U, Y, g, i, j, x0, y0, f.d1[0], f.d1[1], w1, R1);
+    const bool low1 = TAYLOR && p.kx * fabs(f.d1[0]) + p.ky * fabs(f.d1[1]) <= T(kTaylorMax2);
+    if (!low1) order4();
+    if (low1) {
+        T sx, sy, sxx, sxy, syy;
+        stream_taylor2(jet, f.d1[0], f.d1[1], sx, sy, sxx, sxy, syy);
+        from_stream(sx, sy, sxx, sxy, syy, T(1), w1, R1);
+    } else {
+        stream_stage<T, TAYLOR>(p, jet, U, Y, g, i, j, x0, y0, f.d1[0], f.d1[1], w1, R1);
+    }
     // stage 3 at x2 = x - dt (v0 + v1) / 4, time t + dt/2
     f.d2[0] = -(st.q1 * w0[0] + st.q2 * w1[0]);
     f.d2[1] = -(st.q1 * w0[1] + st.q2 * w1[1]);
-    stream_stage<T, TAYLOR>(p, jet, U, Y, g, i, j, x0, y0, f.d2[0], f.d2[1], w2, R2);
+    const bool low2 = TAYLOR && p.kx * fabs(f.d2[0]) + p.ky * fabs(f.d2[1]) <= T(kTaylorMax2);
+    if (low1 && !low2) order4();  // the order-4 jet was not needed until now
+    if (low2) {
+        T sx, sy, sxx, sxy, syy;
+        stream_taylor2(jet, f.d2[0], f.d2[1], sx, sy, sxx, sxy, syy);
+        from_stream(sx, sy, sxx, sxy, syy, T(1), w2, R2);
+    } else {
+        stream_stage<T, TAYLOR>(p, jet, U, Y, g, i, j, x0, y0, f.d2[0], f.d2[1], w2, R2);
+    }
 #pragma unroll
     for (int a = 0; a < 2; a++) {
         f.v0[a] = st.c1 * w0[a];

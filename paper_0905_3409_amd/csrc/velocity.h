@@ -151,6 +151,67 @@ __device__ __forceinline__ void stream_modes(const Params &p, const T *sx, const
     from_stream(fx, fy, fxx, fxy, fyy, c, v, J);
 }
 
+// The same five sums from sin and cos of pi x and pi y at the point alone,
+// contracted over m first: A_n = sum_m S[m][n] (m pi) cos(m pi x),
+// B_n = sum_m S[m][n] sin(m pi x), C_n = sum_m S[m][n] (m pi)^2 sin(m pi x);
+// then s_x = sum_n sin(n pi y) A_n, s_xy = sum_n (n pi) cos(n pi y) A_n,
+// s_y = sum_n (n pi) cos(n pi y) B_n, s_yy = -sum_n (n pi)^2 sin(n pi y) B_n,
+// s_xx = -sum_n sin(n pi y) C_n. The multiples of each angle come from the
+// recurrence of multiples_from one at a time, so only the twelve partial sums
+// and the recurrence are live (fewer registers than the sums over tabulated
+// multiples; the same values up to the order of the additions).
+template <typename T, class Params>
+__device__ __forceinline__ void stream_modes_from(const Params &p, T s1x, T c1x, T s1y, T c1y,
+                                                  T c, T *v, T *J)
+{
+    T A[4], B[4], C[4];
+    {
+        const T t = T(2) * c1x;
+        T sm = s1x, cm = c1x, sp = T(0), cp = T(1);  // sin, cos of (m+1) pi x and m pi x
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            const T km = T((m + 1) * kPi);
+            const T kc = km * cm, ks = km * km * sm;
+#pragma unroll
+            for (int n = 0; n < 4; n++) {
+                if (m == 0) {
+                    A[n] = p.S[m][n] * kc;
+                    B[n] = p.S[m][n] * sm;
+                    C[n] = p.S[m][n] * ks;
+                } else {
+                    A[n] += p.S[m][n] * kc;
+                    B[n] += p.S[m][n] * sm;
+                    C[n] += p.S[m][n] * ks;
+                }
+            }
+            const T sn = t * sm - sp, cn = t * cm - cp;
+            sp = sm;
+            cp = cm;
+            sm = sn;
+            cm = cn;
+        }
+    }
+    T fx = 0, fy = 0, fxx = 0, fyy = 0, fxy = 0;
+    const T t = T(2) * c1y;
+    T sn = s1y, cn = c1y, sp = T(0), cp = T(1);
+#pragma unroll
+    for (int n = 0; n < 4; n++) {
+        const T kn = T((n + 1) * kPi);
+        const T qy = kn * cn, ry = kn * kn * sn;
+        fx += sn * A[n];
+        fxy += qy * A[n];
+        fy += qy * B[n];
+        fyy -= ry * B[n];
+        fxx -= sn * C[n];
+        const T s2 = t * sn - sp, c2 = t * cn - cp;
+        sp = sn;
+        cp = cn;
+        sn = s2;
+        cn = c2;
+    }
+    from_stream(fx, fy, fxx, fxy, fyy, c, v, J);
+}
+
 template <typename T, class Params>
 __device__ __forceinline__ void vel_stream(const Params &p, const double *x, T c, T *v, T *J)
 {

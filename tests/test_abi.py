@@ -461,3 +461,34 @@ def test_noalloc_advance_validation_on_host_only_context():
         assert L.gals_advance_noalloc(ctx, phi, vp(0x100000000), 0.0, 0.1, 1, None) == pkg.EINVAL
         assert (b"static scratch" in L.gals_last_error()) == (not fits)
         L.gals_destroy(ctx)
+
+
+def _shape_key(prec, mixed, ncells):
+    """FNV-1a over 64-bit little-endian words, as the library keys a batch
+    shape for its tuning record."""
+    h = 14695981039346656037
+    for v in [prec, mixed, len(ncells)] + [c for nc in ncells for c in nc]:
+        for k in range(8):
+            h ^= (v >> (8 * k)) & 0xFF
+            h = (h * 1099511628211) % (1 << 64)
+    return h
+
+
+def test_batch_tuning_record_is_read_at_create(tmp_path, monkeypatch):
+    """A batch of a shape recorded in GALS_TUNE_FILE starts with the recorded
+    wave shapes (the last valid line for the key wins); other shapes, and
+    invalid lines, keep the default."""
+    ncells = [(40, 40), (100, 90), (300, 300)]
+    key = _shape_key(pkg.F32, pkg.MIXED_CENTRAL, ncells)
+    f = tmp_path / "tune.txt"
+    f.write_text(f"{key:016x} 32 32 32 32\n"
+                 f"{key ^ 1:016x} 16 16 16 16\n"
+                 f"{key:016x} 0 16 32 64\n"
+                 f"{key:016x} 7 7 7 7\n")
+    monkeypatch.setenv("GALS_TUNE_FILE", str(f))
+    b = pkg.Batch(ncells, dtype="float32", device=-1)
+    assert b.get_tiles() == [0, 16, 32, 64]
+    other = pkg.Batch(ncells[:2], dtype="float32", device=-1)
+    assert other.get_tiles() == [64, 64, 64, 64]
+    monkeypatch.delenv("GALS_TUNE_FILE")
+    assert pkg.Batch(ncells, dtype="float32", device=-1).get_tiles() == [64, 64, 64, 64]

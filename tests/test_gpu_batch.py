@@ -170,6 +170,21 @@ def test_autotune_picks_valid_shapes():
         _assert_same(b.to_numpy(st, k), _single(p, w, "float32", 0.0, 2), f"problem {k}")
 
 
+def test_autotune_choice_is_recorded_for_the_batch_shape(tmp_path, monkeypatch):
+    """After an autotune, a new batch of the same shape starts with the tuned
+    wave shapes, and the choice is appended to GALS_TUNE_FILE."""
+    f = tmp_path / "tune.txt"
+    monkeypatch.setenv("GALS_TUNE_FILE", str(f))
+    w = _workload(seed=19)
+    b, st = _batch(w, "float32")
+    b.autotune(st.clone(), w["dt"], steps=2)
+    tuned = b.get_tiles()
+    again = pkg.Batch([p["ncell"] for p in w["problems"]], dtype="float32")
+    assert again.get_tiles() == tuned
+    lines = f.read_text().split()
+    assert len(lines) == 5 and [int(v) for v in lines[1:]] == tuned
+
+
 def test_zero_steps_leave_state_untouched():
     import torch
     w = _workload(sizes=SIZES[:3], seed=18)
