@@ -61,15 +61,23 @@ HBM_PEAK_GBPS = 8000.0
 # (The 157.3 TFLOP/s datasheet figure needs packed FP32 instructions, which this
 # build does not emit.)
 VALU_F32_PEAK_TFLOPS = 78.6
+SIMDS = 256 * 4
+CLOCK_GHZ = 2.4
 VALU_F32_PACKED_PEAK_TFLOPS = 157.3  # reported beside it, for comparison only
 # Floating-point operations per node of the FP32 stream-function step as
-# formulated, FMA = 2: jet 98 (14 dot products of 4), stage 1 0 (signs only:
-# dt and the time factors sit in the stage weights), stage 2 75 (offset 2,
-# Taylor test 3, offset scalings 4, Taylor polynomials 66), stage 3 79
-# (offset 6), Jacobian chain 66, foot (displacement in FP32, position in
-# FP64) and split 16, cross derivatives 8, Hermite weights 40, bicubic value
-# and gradient 80, gradient update 6.
+# formulated, FMA = 2, on a lane whose stages take the degree-3 Taylor
+# polynomials: jet 98 (14 dot products of 4), stage 1 0 (signs only: dt and
+# the time factors sit in the stage weights), stage 2 75 (offset 2, Taylor
+# test 3, offset scalings 4, Taylor polynomials 66), stage 3 79 (offset 6),
+# Jacobian chain 66, foot (displacement in FP32, position in FP64) and split
+# 16, cross derivatives 8, Hermite weights 40, bicubic value and gradient 80,
+# gradient update 6.
 ALG_FLOPS_PER_NODE = 468
+# A lane whose two stage offsets are both in the degree-2 tier: each stage's
+# polynomials cost 32 with 2 scalings (36 fewer a stage), and the jet skips
+# its 5 order-4 entries (35 fewer). A lower bound of the step's count; the
+# headline reports the hardware count from the counter summary instead.
+ALG_FLOPS_PER_NODE_LOW = ALG_FLOPS_PER_NODE - 2 * 36 - 35
 BYTES_PER_NODE = 24  # FP32 state: 3 planes read once + 3 planes written once
 # The cell-based (B) cross derivatives replace the 8 flops of the central
 # differences by 4 edge differences and 4 weighted vertex sums (28 flops).
@@ -155,20 +163,49 @@ def kernel_source_hash(files):
     return h.hexdigest()[:16]
 
 
-def traffic_record(profile_md, files):
-    """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
-    scaled by the counters' reading of a plain copy; None if the kernel has
-    changed since the counters were taken."""
+def profile_record(profile_md, files, kind):
+    """The fields of a `<kind>-record:` line of a committed rocprofv3 summary
+    under profiles/, as floats; None if the summary or the line is missing, or
+    if the kernel has changed since the counters were taken."""
     import re
     path = os.path.join(ROOT, "profiles", profile_md)
     if not os.path.exists(path):
         return None
-    m = re.search(r"traffic-record: src_hash=(\w+) fetch_kib=([\d.]+) write_kib=([\d.]+) "
-                  r"fetch_scale=([\d.]+) write_scale=([\d.]+)", open(path).read())
+    m = re.search(kind + r"-record: src_hash=(\w+)((?: \w+=[\d.]+)+)", open(path).read())
     if not m or m.group(1) != kernel_source_hash(files):
         return None
-    kib = float(m.group(2)) * float(m.group(4)) + float(m.group(3)) * float(m.group(5))
+    return {k: float(v) for k, v in re.findall(r"(\w+)=([\d.]+)", m.group(2))}
+
+
+def traffic_record(profile_md, files):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
+    scaled by the counters' reading of a plain copy; None if the kernel has
+    changed since the counters were taken."""
+    r = profile_record(profile_md, files, "traffic")
+    if r is None:
+        return None
+    kib = r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"]
     return kib * 1024.0
+
+
+def valu_issue(profile_md, files, kernel_us):
+    """The vector-issue side of a kernel from its rocprofv3 counter summary:
+    VALU instructions per wave (SQ_INSTS_VALU / SQ_WAVES), hardware flops per
+    node (SQ_INSTS_VALU_FLOPS_FP32 + _FP64, x64 lanes, over the nodes), and
+    the time the chip needs to issue those instructions at 4 cycles per wave64
+    instruction (16 lanes per SIMD) on 1024 SIMDs at 2.4 GHz, as a fraction
+    of the kernel's measured time. None if the kernel has changed since."""
+    r = profile_record(profile_md, files, "valu")
+    if r is None:
+        return None
+    issue_us = r["valu_per_wave"] * r["waves"] * 4 / (SIMDS * CLOCK_GHZ * 1e3)
+    tflops = r["hw_flops_per_node"] * r["nodes"] / (kernel_us * 1e-6) / 1e12
+    return {"valu_instr_per_wave": r["valu_per_wave"], "waves": int(r["waves"]),
+            "issue_us_at_4_cycles": issue_us, "issue_frac": issue_us / kernel_us,
+            "hw_flops_per_node": r["hw_flops_per_node"], "hw_tflops": tflops,
+            "hw_frac_of_nonpacked_fp32_peak": tflops / VALU_F32_PEAK_TFLOPS,
+            "hw_frac_of_packed_fp32_peak": tflops / VALU_F32_PACKED_PEAK_TFLOPS,
+            "source": "profiles/" + profile_md}
 
 
 def main():
@@ -306,8 +343,12 @@ def main():
     res["fp32_linf_band_error"] = n32[3]
 
     gbps = nodes * BYTES_PER_NODE / (kernel_us * 1e-6) / 1e9
-    tflops = nodes * ALG_FLOPS_PER_NODE / (kernel_us * 1e-6) / 1e12
     state_bytes = 3 * g32.plane * 4
+    # the vector-issue side, from the kernel's committed counter summary
+    alu = {"nonpacked_fp32_peak_tflops": VALU_F32_PEAK_TFLOPS,
+           "packed_fp32_peak_tflops": VALU_F32_PACKED_PEAK_TFLOPS}
+    alu.update(valu_issue("k_step2d_f32_stream_2048.md", SINGLE_KERNEL_SOURCES, kernel_us)
+               or {"source": None})
     roofline = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": gbps / HBM_PEAK_GBPS,
                 "traffic": traffic_record("k_step2d_f32_stream_2048.md", SINGLE_KERNEL_SOURCES),
@@ -317,14 +358,10 @@ def main():
                 "working_set_bytes": 2 * state_bytes,
                 "mall_resident": 2 * state_bytes < MALL_BYTES,
                 "note": "the two 50 MB state copies fit the 256 MB Infinity Cache, so these "
-                        "bytes are not all HBM traffic; the kernel is bound by its vector ALU "
-                        "(alu below), the 8192^2 probe (--workload probe) by neither",
-                "alu": {"achieved_tflops": tflops, "flops_per_node": ALG_FLOPS_PER_NODE,
-                        "flops_per_launch": nodes * ALG_FLOPS_PER_NODE,
-                        "frac_of_nonpacked_fp32_peak": tflops / VALU_F32_PEAK_TFLOPS,
-                        "nonpacked_fp32_peak_tflops": VALU_F32_PEAK_TFLOPS,
-                        "frac_of_packed_fp32_peak": tflops / VALU_F32_PACKED_PEAK_TFLOPS,
-                        "packed_fp32_peak_tflops": VALU_F32_PACKED_PEAK_TFLOPS}}
+                        "bytes are not all HBM traffic; the kernel is bound by vector "
+                        "instruction issue (alu.issue_frac: the time its VALU instructions "
+                        "need at 4 cycles each, over its measured time)",
+                "alu": alu}
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
@@ -690,15 +727,21 @@ def bench_batched(args):
     value = nodes * inner / (ms_per_step * 1e-3)
     log(f"batched fp32: {ms_per_step:.2f} ms/bench step, advance {adv_ms:.2f} ms, "
         f"{kernel_us:.2f} us per step launch, {value / 1e9:.2f} G node-upd/s")
-    tflops = nodes * ALG_FLOPS_PER_NODE / (kernel_us * 1e-6) / 1e12
+    # flops per node: the hardware count of the committed counter summary
+    # while it matches the kernel's source, else the formulated lower bound
+    issue = valu_issue("k_batch_step_f32_512grids.md", BATCH_KERNEL_SOURCES, kernel_us)
+    fpn = issue["hw_flops_per_node"] if issue else ALG_FLOPS_PER_NODE_LOW
+    tflops = nodes * fpn / (kernel_us * 1e-6) / 1e12
     gbps = nodes * BYTES_PER_NODE / (kernel_us * 1e-6) / 1e9
     roofline = {"bound": "alu", "achieved": tflops, "peak": VALU_F32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": tflops / VALU_F32_PEAK_TFLOPS,
                 "traffic": traffic_record("k_batch_step_f32_512grids.md", BATCH_KERNEL_SOURCES),
                 "kernel": "k_batch_step<float, CENTRAL, taylor>",
-                "flops_per_launch": nodes * ALG_FLOPS_PER_NODE, "avg_launch_us": kernel_us,
+                "flops_per_node": fpn,
+                "flops_counted": "hardware (rocprofv3)" if issue else "formulated lower bound",
+                "flops_per_launch": nodes * fpn, "avg_launch_us": kernel_us,
                 "hbm_gbps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS,
-                "bytes_per_launch": nodes * BYTES_PER_NODE}
+                "bytes_per_launch": nodes * BYTES_PER_NODE, "valu": issue}
     cpu = None
     if not args.no_cpu:
         import oracle
