@@ -178,6 +178,7 @@ __device__ __forceinline__ void pstore_nt(T *base, unsigned elem, T v)
 template <typename T>
 struct AffineMap {
     double Mc[9], kc[3];  // foot in cell units: s_a = kc_a + sum_b Mc[a][b] idx_b
+    double Md[9];         // Mc - I: the displacement in cells s_a - idx_a = kc_a + sum_b Md[a][b] idx_b
     T J[9];               // Jacobian of the foot map (J form), uniform
     T An[9], Af[9];       // Heun: grad v at the node (t + dt) and at the foot (t)
 };
@@ -244,6 +245,7 @@ static AffineMap<T> make_affine_map(const gals_ctx *ctx, double dt, double c1, d
         }
         am.kc[a] = k / g.h[a];
     }
+    for (int k = 0; k < 9; k++) am.Md[k] = am.Mc[k] - double(k % 4 == 0);
     for (int i = 0; i < D; i++)
         for (int j = 0; j < D; j++) {
             am.J[i * D + j] = T(M[i * 3 + j]);
@@ -251,6 +253,19 @@ static AffineMap<T> make_affine_map(const gals_ctx *ctx, double dt, double c1, d
             am.Af[i * D + j] = T(c2 * A[i * 3 + j]);
         }
     return am;
+}
+
+template <typename T>
+__device__ __forceinline__ void split_cell_axis(const Geom &g, int a, double s, int &cell, T &xi,
+                                                bool &outb)
+{
+    const bool below = s < g.lowc[a], above = s > g.outc[a];
+    const double fl = fmin(fmax(floor(s), 0.0), g.lastc[a]);
+    cell = int(fl);
+    T x = T(s - fl);
+    x = below ? T(0) : x;
+    xi = above ? T(1) : x;
+    outb = below || above;
 }
 
 // Boundary treatment and split of a foot given in cell units: outside only
@@ -262,14 +277,56 @@ __device__ __forceinline__ void split_cells(const Geom &g, const double *s, int 
                                             bool *outb)
 {
 #pragma unroll
+    for (int a = 0; a < D; a++) split_cell_axis(g, a, s[a], cell[a], xi[a], outb[a]);
+}
+
+// The same for an FP32 state from the displacement in cells e = s - idx
+// (FP64, rounded to FP32 here: one rounding, u |e|): with c = floor(e), a
+// foot whose cell idx + c lies in [0, nc-1] (not outside, not clamped)
+// splits into cell idx + c and local coordinate e - c, both exact in FP32.
+// Only the other lanes take the FP64 treatment of split_cells (from
+// s = idx + e), and a wave without such lanes skips it; each lane's result
+// is the same either way.
+template <typename T, int D>
+__device__ __forceinline__ void split_disp(const Geom &g, const int *idx, const double *e64,
+                                           int *cell, T *xi, bool *outb)
+{
+    static_assert(sizeof(T) == 4, "FP32 states only");
+    float e[D], c[D];
+    int cu[D];
+    bool in = true;
+#pragma unroll
     for (int a = 0; a < D; a++) {
-        const bool below = s[a] < g.lowc[a], above = s[a] > g.outc[a];
-        const double fl = fmin(fmax(floor(s[a]), 0.0), g.lastc[a]);
-        cell[a] = int(fl);
-        T x = T(s[a] - fl);
-        x = below ? T(0) : x;
-        xi[a] = above ? T(1) : x;
-        outb[a] = below || above;
+        e[a] = float(e64[a]);
+        c[a] = floor(e[a]);
+        cu[a] = idx[a] + int(c[a]);
+        in = in && unsigned(cu[a]) <= unsigned(g.nc[a] - 1);
+    }
+    if (__all(in)) {
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            cell[a] = cu[a];
+            xi[a] = e[a] - c[a];
+            outb[a] = false;
+        }
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        const float fr = e[a] - c[a];
+        if (unsigned(cu[a]) <= unsigned(g.nc[a] - 1)) {
+            cell[a] = cu[a];
+            xi[a] = fr;
+            outb[a] = false;
+        } else if (cu[a] == g.nc[a] && double(fr) <= g.outc[a] - g.ncd[a]) {
+            // at most kFootTol past the last node: the last cell at local
+            // coordinate 1 + fr (split_cells' rule, evaluated in FP32)
+            cell[a] = g.nc[a] - 1;
+            xi[a] = 1.0f + fr;
+            outb[a] = false;
+        } else {
+            split_cell_axis(g, a, double(idx[a]) + e64[a], cell[a], xi[a], outb[a]);
+        }
     }
 }
 
@@ -337,11 +394,20 @@ __global__ __launch_bounds__(kBlock) void k_step2d_affine(Geom g, TileGrid tg, A
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int j = __builtin_amdgcn_readfirstlane(ry0 + kHaloY + int(threadIdx.y) + 4 * r);
-        double sc[2];
+        if constexpr (sizeof(T) == 4) {
+            const int idx[2] = {i, j};
+            double e[2];
 #pragma unroll
-        for (int a = 0; a < 2; a++)
-            sc[a] = am.kc[a] + am.Mc[a * 3] * double(i) + am.Mc[a * 3 + 1] * double(j);
-        split_cells<T, 2>(g, sc, cell[r], xi[r], outb[r]);
+            for (int a = 0; a < 2; a++)
+                e[a] = am.kc[a] + am.Md[a * 3] * double(i) + am.Md[a * 3 + 1] * double(j);
+            split_disp<T, 2>(g, idx, e, cell[r], xi[r], outb[r]);
+        } else {
+            double sc[2];
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+                sc[a] = am.kc[a] + am.Mc[a * 3] * double(i) + am.Mc[a * 3 + 1] * double(j);
+            split_cells<T, 2>(g, sc, cell[r], xi[r], outb[r]);
+        }
     }
     stager.store(tile);
     __syncthreads();
