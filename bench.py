@@ -742,6 +742,57 @@ def bench_batched(args):
                 "flops_per_launch": nodes * fpn, "avg_launch_us": kernel_us,
                 "hbm_gbps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS,
                 "bytes_per_launch": nodes * BYTES_PER_NODE, "valu": issue}
+    # the FP32 final states of every 8th grid against an FP64 batched run of
+    # the same steps (the FP64 batch matches the oracle; its grids are
+    # checked against FP64 single grids bit for bit in the tests)
+    res = {}
+    if not args.no_fp64:
+        # one advance of `inner` steps from the initial state, as timed
+        st.copy_(ref)
+        bench_step()
+        torch.cuda.synchronize()
+        fin32 = {k: b.to_numpy(st, k) for k in range(0, len(probs), 8)}
+        b64 = pkg.Batch([p["ncell"] for p in probs], dtype="float64")
+        for k, p in enumerate(probs):
+            b64.set_velocity(k, w["kind"], p["params"], w["period"])
+        st64 = b64.from_numpy([(p["phi0"], p["psi0"]) for p in probs])
+        b64.advance(st64, 0.0, w["dt"], inner)
+        torch.cuda.synchronize()
+        rows = []
+        for k, f32 in fin32.items():
+            p = probs[k]
+            gk = pkg.Grid(p["ncell"], (0.0, 0.0), (1.0, 1.0), dtype="float64")
+            hk = 1.0 / max(p["ncell"])
+            ref = gk.from_numpy(*b64.to_numpy(st64, k))
+            d = state_errors(gk, gk.from_numpy(*f32), ref, hk, 1.5 * hk, 3 * hk)
+            n0 = gk.norms(ref, gk.from_numpy(p["phi0"], p["psi0"]), 1.5 * hk, 3 * hk)
+            # resolved: the FP64 run returns phi to within twice its initial
+            # range (on the coarsest grids the flow's filaments are not
+            # resolved, |psi| grows by orders of magnitude in both precisions,
+            # and the two runs differ at O(1))
+            resolved = d["max_abs_phi_ref"] <= 2.0 * float(np.max(np.abs(p["phi0"])))
+            rows.append((max(p["ncell"]), resolved, d["phi"], d["psi"], d["psi_scaled"],
+                         d["l1_shape"] / n0[2] if n0[2] > 0 else 0.0))
+            del gk, ref
+        ok = [r for r in rows if r[1]]
+        cols = ("phi", "psi", "psi_scaled", "l1_shape_rel")
+        res["fp32_vs_fp64_final"] = {
+            "grids": len(rows), "resolved_grids": len(ok),
+            "smallest_resolved_cells": min(r[0] for r in ok) if ok else None,
+            "largest_unresolved_cells": max((r[0] for r in rows if not r[1]), default=None),
+            "median_resolved": {c: float(np.median([r[2 + i] for r in ok])) for i, c in enumerate(cols)} if ok else None,
+            "worst_resolved": {c: float(max(r[2 + i] for r in ok)) for i, c in enumerate(cols)} if ok else None,
+            "how": "every 8th grid, FP32 final state against an FP64 batched run of the same steps; "
+                   "l1_shape_rel: the L1 shape distance between the two final states over the FP64 "
+                   "run's own L1 shape error against the initial state"}
+        f = res["fp32_vs_fp64_final"]
+        if ok:
+            log(f"fp32 vs fp64 final ({f['resolved_grids']} of {f['grids']} sampled grids resolved, "
+                f"the smallest {f['smallest_resolved_cells']} cells): median phi "
+                f"{f['median_resolved']['phi']:.2e} psi {f['median_resolved']['psi']:.2e}, worst phi "
+                f"{f['worst_resolved']['phi']:.2e} psi {f['worst_resolved']['psi']:.2e}, L1 shape "
+                f"distance {f['worst_resolved']['l1_shape_rel']:.2e} of the FP64 shape error")
+        del b64, st64
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -759,17 +810,20 @@ def bench_batched(args):
                          f"({len(sample)} grids, {snodes} nodes; FP64 oracle, OpenMP), "
                          f"{c - a:.1f} s"}
         log(f"cpu oracle: {cpu['value'] / 1e6:.2f} M node-upd/s on {cpu['cores']} threads")
-        # and on one core: the first step
+        # and on one core: the same sample, one step
         threads = oracle.num_threads()
         oracle.set_threads(1)
         a = time.perf_counter()
-        oracle.advance(2, w["ncell"], w["lo"], w["hi"], w["kind"], w["params"], w["period"],
-                       w["phi0"], w["psi0"], 0.0, w["dt"], 1)
-        b = time.perf_counter()
+        for k in sample:
+            p = probs[k]
+            oracle.advance(2, p["ncell"], (0.0, 0.0), (1.0, 1.0), w["kind"], p["params"],
+                           w["period"], p["phi0"], p["psi0"], 0.0, w["dt"], 1)
+        c = time.perf_counter()
         oracle.set_threads(threads)
-        cpu["single_core"] = {"value": nodes / (b - a), "unit": "node-updates/s", "cores": 1,
-                              "sample": f"the first step, {b - a:.1f} s"}
-        log(f"cpu oracle, 1 core: {nodes / (b - a) / 1e6:.3f} M node-upd/s")
+        cpu["single_core"] = {"value": snodes / (c - a), "unit": "node-updates/s", "cores": 1,
+                              "sample": f"the first step of the same {len(sample)} grids, "
+                                        f"{c - a:.1f} s"}
+        log(f"cpu oracle, 1 core: {snodes / (c - a) / 1e6:.3f} M node-upd/s")
     line = {
         "metric": "GALS batched node-updates/s (512 uneven 2D grids, one launch per step)",
         "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -785,6 +839,7 @@ def bench_batched(args):
         "hbm_gbps_algorithmic": gbps,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        **res,
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -1196,6 +1251,7 @@ def bench_3d(args):
     log(f"fp32: advance {adv_ms:.1f} ms, step kernel {kernel_us:.1f} us, "
         f"{value / 1e9:.2f} G node-upd/s, L1 shape err {n32[2]:.3e}; 1e6 point evals "
         f"{eval_ms:.3f} ms")
+    fin32 = g32.to_numpy(st32)  # the FP32 final state, for the comparison with FP64
     del g32, st32, ref32
     torch.cuda.empty_cache()
     res = {}
@@ -1205,8 +1261,13 @@ def bench_3d(args):
         res["fp64"] = {"value": nodes * inner / (t64[0] * 1e-3), "advance_ms": t64[0],
                        "l1_shape_error": n64[2], "linf_band_error": n64[3]}
         res["l1_shape_error_ratio_fp32_over_fp64"] = n32[2] / n64[2] if n64[2] > 0 else None
+        # the FP32 final state against the FP64 one (the FP64 path matches the
+        # oracle to 1e-12), both after the whole run
+        d = state_errors(g64, g64.from_numpy(*fin32), st64, h, eps, band)
+        res["fp32_vs_fp64_final"] = d
         log(f"fp64: advance {t64[0]:.1f} ms, {res['fp64']['value'] / 1e9:.2f} G node-upd/s, "
-            f"L1 shape err {n64[2]:.3e}")
+            f"L1 shape err {n64[2]:.3e}; fp32 vs fp64 final: phi {d['phi']:.2e} "
+            f"psi {d['psi']:.2e} L1 {d['l1_shape']:.2e}")
         del g64, st64, ref64
     gbps = nodes * BYTES_PER_NODE_3D / (kernel_us * 1e-6) / 1e9
     tflops = nodes * FLOPS_PER_NODE_3D / (kernel_us * 1e-6) / 1e12
