@@ -96,7 +96,12 @@ __device__ __forceinline__ void mode_terms(T c, const T *vb, const T *Ab, const 
     for (int m = 0; m < 4; m++) {
         const T M2 = T((m + 1) * (m + 1) * kPi * kPi);
 #pragma unroll
-        for (int n = 0; n < 4; n++) acc[4 * m + n] += sx[m] * (p[n] + M2 * q[n]) + mc[m] * r[n];
+        for (int n = 0; n < 4; n++) {
+            // one multiply-add per statement (as one expression the two
+            // products would cost a multiply, a multiply-add and an add)
+            acc[4 * m + n] += sx[m] * (p[n] + M2 * q[n]);
+            acc[4 * m + n] += mc[m] * r[n];
+        }
     }
 }
 

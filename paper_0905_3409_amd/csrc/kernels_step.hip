@@ -622,19 +622,15 @@ __device__ __forceinline__ void modes_at(const Vel<T> &p, T (*tab)[kBlock], cons
 
 template <typename T, bool SHIFT, bool LDS>
 __device__ __forceinline__ void stage_vecpot(const Vel<T> &p, T (*tab)[kBlock], const T *s1,
-                                             const T *c1, const double *x, const double *xs,
-                                             T cf, T *v, T *A)
+                                             const T *c1, const double *x, const T *d, T *w,
+                                             T *R)
 {
     T sx[4], cx[4], sy[4], cy[4], sz[4], cz[4];
     // FP32: the short series up to |pi d| = kShiftMax; FP64: the long one
     constexpr double kMax = sizeof(T) == 4 ? kShiftMax : kShiftMaxLong<T>;
     bool near = SHIFT;
-    T d[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        d[a] = T(xs[a] - x[a]);
-        near = near && fabs(d[a]) <= T(kMax / kPi);
-    }
+    for (int a = 0; a < 3; a++) near = near && fabs(d[a]) <= T(kMax / kPi);
     if (near) {
         T s[3], c[3];
 #pragma unroll
@@ -648,11 +644,11 @@ __device__ __forceinline__ void stage_vecpot(const Vel<T> &p, T (*tab)[kBlock], 
         multiples_from(s[1], c[1], sy, cy);
         multiples_from(s[2], c[2], sz, cz);
     } else {
-        sincos_multiples(T(xs[0]), sx, cx);
-        sincos_multiples(T(xs[1]), sy, cy);
-        sincos_multiples(T(xs[2]), sz, cz);
+        sincos_multiples(T(x[0] + double(d[0])), sx, cx);
+        sincos_multiples(T(x[1] + double(d[1])), sy, cy);
+        sincos_multiples(T(x[2] + double(d[2])), sz, cz);
     }
-    modes_at<T, LDS>(p, tab, sx, cx, sy, cy, sz, cz, cf, v, A);
+    modes_at<T, LDS>(p, tab, sx, cx, sy, cy, sz, cz, T(1), w, R);
 }
 
 // Five waves per SIMD for the FP32 superconsistent kernel: about 93 VGPRs
@@ -688,31 +684,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         s1[a] = tab[2 * ti[a]];
         c1[a] = tab[2 * ti[a] + 1];
     }
-    T v0[3], A0[9], v1[3], A1[9], v2[3], A2[9];
+    // w_k, R_k: velocity and velocity Jacobian at stage k without the time
+    // factor c_k (Stage carries dt c_k in its weights, as in the 2D stream
+    // step); the stage offsets and the foot's displacement are summed in T,
+    // the foot itself in FP64
+    T w0[3], R0[9], w1[3], R1[9], w2[3], R2[9];
     {
         T sx[4], cx[4], sy[4], cy[4], sz[4], cz[4];
         multiples_from(s1[0], c1[0], sx, cx);
         multiples_from(s1[1], c1[1], sy, cy);
         multiples_from(s1[2], c1[2], sz, cz);
-        modes_at<T, LDS>(p, tab_s, sx, cx, sy, cy, sz, cz, st.c1, v0, A0);  // v(x, t + dt)
+        modes_at<T, LDS>(p, tab_s, sx, cx, sy, cy, sz, cz, T(1), w0, R0);  // at x, t + dt
     }
-    double x1[3], x2[3], X[3];
+    T d1[3], d2[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) x1[a] = x[a] - dt * double(v0[a]);
-    stage_vecpot<T, SHIFT, LDS>(p, tab_s, s1, c1, x, x1, st.c2, v1, A1);  // v(x1, t)
+    for (int a = 0; a < 3; a++) d1[a] = -st.e1 * w0[a];
+    stage_vecpot<T, SHIFT, LDS>(p, tab_s, s1, c1, x, d1, w1, R1);  // at x1 = x + d1, t
 #pragma unroll
-    for (int a = 0; a < 3; a++) x2[a] = x[a] - dt * (0.25 * double(v0[a]) + 0.25 * double(v1[a]));
-    stage_vecpot<T, SHIFT, LDS>(p, tab_s, s1, c1, x, x2, st.c3, v2, A2);  // v(x2, t + dt/2)
+    for (int a = 0; a < 3; a++) d2[a] = -(st.q1 * w0[a] + st.q2 * w1[a]);
+    stage_vecpot<T, SHIFT, LDS>(p, tab_s, s1, c1, x, d2, w2, R2);  // at x2 = x + d2, t + dt/2
+    double X[3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
-        X[a] = x[a] - dt * (double(v0[a]) * (1.0 / 6.0) + double(v1[a]) * (1.0 / 6.0) +
-                            double(v2[a]) * (2.0 / 3.0));
+        X[a] = x[a] - double(st.f1 * w0[a] + st.f2 * w1[a] + st.f3 * w2[a]);
     T J[9];
     if constexpr (PSI == GALS_PSI_SUPERCONSISTENT) {
-        jacobian_chain<T, 3>(A0, A1, A2, T(dt), J);
+        jacobian_chain_w<T, 3>(R0, R1, R2, st, J);
     } else {
 #pragma unroll
-        for (int q = 0; q < 9; q++) J[q] = A0[q];
+        for (int q = 0; q < 9; q++) J[q] = st.c1 * R0[q];
     }
     finish3d<T, GALS_VEL_VECPOT_SIN, MIX, PSI>(g, p, st, dt, i, j, k, X, J, phi, grad, phi_o,
                                               grad_o);

@@ -251,6 +251,41 @@ __device__ __forceinline__ void vel_pseudo1d(const double *x, T c, T *v, T *J)
     J[3] = E * e1 * e1;
 }
 
+// One mode's terms of vecpot_modes added into the sums, one product per
+// statement: each is a single multiply-add into its sum (a term pair written
+// as one expression would cost a multiply, a multiply-add and an add).
+template <typename T>
+__device__ __forceinline__ void vecpot_accumulate(const T *q, T SSS, T SCS, T SSC, T SCC, T CSS,
+                                                  T CCS, T CSC, T &vx, T &vy, T &vz, T &j00,
+                                                  T &j01, T &j02, T &j10, T &j11, T &j12,
+                                                  T &j20, T &j21, T &j22)
+{
+    vx += q[0] * SCS;
+    vx -= q[1] * SSC;
+    vy += q[2] * SSC;
+    vy -= q[3] * CSS;
+    vz += q[4] * CSS;
+    vz -= q[5] * SCS;
+    j00 += q[6] * CCS;
+    j00 -= q[7] * CSC;
+    j01 -= q[8] * SSS;
+    j01 -= q[9] * SCC;
+    j02 += q[10] * SCC;
+    j02 += q[11] * SSS;
+    j10 += q[12] * CSC;
+    j10 += q[13] * SSS;
+    j11 += q[14] * SCC;
+    j11 -= q[6] * CCS;
+    j12 -= q[15] * SSS;
+    j12 -= q[16] * CSC;
+    j20 -= q[17] * SSS;
+    j20 -= q[18] * CCS;
+    j21 += q[19] * CCS;
+    j21 += q[20] * SSS;
+    j22 += q[7] * CSC;
+    j22 -= q[14] * SCC;
+}
+
 // v = curl A, A = sum_k a_k sin(l pi x) sin(m pi y) sin(n pi z). Per mode the
 // seven products of sines (S) and cosines (C) in x, y, z are formed once and
 // combined with precomputed coefficients a_c K_i (K_j) (K = wavenumber * pi):
@@ -271,19 +306,8 @@ __device__ __forceinline__ void vecpot_modes(const Vel<T> &p, const T *sx, const
         const T ss = Sy * Sz, cs = Cy * Sz, sc = Sy * Cz, cc = Cy * Cz;
         const T SSS = Sx * ss, SCS = Sx * cs, SSC = Sx * sc, SCC = Sx * cc;
         const T CSS = Cx * ss, CCS = Cx * cs, CSC = Cx * sc;
-        const T *q = p.vpc[k];
-        vx += q[0] * SCS - q[1] * SSC;
-        vy += q[2] * SSC - q[3] * CSS;
-        vz += q[4] * CSS - q[5] * SCS;
-        j00 += q[6] * CCS - q[7] * CSC;
-        j01 -= q[8] * SSS + q[9] * SCC;
-        j02 += q[10] * SCC + q[11] * SSS;
-        j10 += q[12] * CSC + q[13] * SSS;
-        j11 += q[14] * SCC - q[6] * CCS;
-        j12 -= q[15] * SSS + q[16] * CSC;
-        j20 -= q[17] * SSS + q[18] * CCS;
-        j21 += q[19] * CCS + q[20] * SSS;
-        j22 += q[7] * CSC - q[14] * SCC;
+        vecpot_accumulate(p.vpc[k], SSS, SCS, SSC, SCC, CSS, CCS, CSC, vx, vy, vz, j00, j01,
+                          j02, j10, j11, j12, j20, j21, j22);
     }
     v[0] = c * vx; v[1] = c * vy; v[2] = c * vz;
     J[0] = c * j00; J[1] = c * j01; J[2] = c * j02;
@@ -310,19 +334,8 @@ __device__ __forceinline__ void vecpot_modes_lds(const Vel<T> &p, const T (*tab)
         const T ss = Sy * Sz, cs = Cy * Sz, sc = Sy * Cz, cc = Cy * Cz;
         const T SSS = Sx * ss, SCS = Sx * cs, SSC = Sx * sc, SCC = Sx * cc;
         const T CSS = Cx * ss, CCS = Cx * cs, CSC = Cx * sc;
-        const T *q = p.vpc[k];
-        vx += q[0] * SCS - q[1] * SSC;
-        vy += q[2] * SSC - q[3] * CSS;
-        vz += q[4] * CSS - q[5] * SCS;
-        j00 += q[6] * CCS - q[7] * CSC;
-        j01 -= q[8] * SSS + q[9] * SCC;
-        j02 += q[10] * SCC + q[11] * SSS;
-        j10 += q[12] * CSC + q[13] * SSS;
-        j11 += q[14] * SCC - q[6] * CCS;
-        j12 -= q[15] * SSS + q[16] * CSC;
-        j20 -= q[17] * SSS + q[18] * CCS;
-        j21 += q[19] * CCS + q[20] * SSS;
-        j22 += q[7] * CSC - q[14] * SCC;
+        vecpot_accumulate(p.vpc[k], SSS, SCS, SSC, SCC, CSS, CCS, CSC, vx, vy, vz, j00, j01,
+                          j02, j10, j11, j12, j20, j21, j22);
     }
     v[0] = c * vx; v[1] = c * vy; v[2] = c * vz;
     J[0] = c * j00; J[1] = c * j01; J[2] = c * j02;
