@@ -83,13 +83,14 @@ BYTES_PER_NODE = 24  # FP32 state: 3 planes read once + 3 planes written once
 # differences by 4 edge differences and 4 weighted vertex sums (28 flops).
 VARIANT_B_FLOPS_PER_NODE = ALG_FLOPS_PER_NODE - 8 + 28
 # FP32 3D step, 6-mode vector potential, central cross derivatives, as the
-# kernel formulates it (FMA = 2): velocity and Jacobian at the node from the
-# per-axis tables (multiples 36, 6 modes x 59, scaling 12: 402) and at the two
-# off-node stages with the angles shifted by angle addition (shift 36,
-# multiples 36, modes 354, scaling 12: 438 each), FP64 stage positions 30,
-# Jacobian chain 216, foot and split 30, cross derivatives 120, Hermite
-# weights 60, tricubic value and gradient 384, gradient update 18.
-FLOPS_PER_NODE_3D = 402 + 2 * 438 + 30 + 216 + 30 + 120 + 60 + 384 + 18
+# kernel formulates it (FMA = 2; the time factors sit in the stage weights):
+# velocity and Jacobian at the node from the per-axis tables (multiples 36,
+# 6 modes x 59: 390) and at the two off-node stages with the angles shifted by
+# angle addition (shift 36, multiples 36, modes 354: 426 each), stage offsets
+# and displacement 30, Jacobian chain 180, foot and split 30, cross
+# derivatives 120, Hermite weights 60, tricubic value and gradient 384,
+# gradient update 18.
+FLOPS_PER_NODE_3D = 390 + 2 * 426 + 30 + 180 + 30 + 120 + 60 + 384 + 18
 BYTES_PER_NODE_3D = 32  # FP32 state: 4 planes read once + 4 planes written once
 # Bandwidth probe (rigid rotation, the cheapest field). The three stages of an
 # affine field compose to one affine map that the host forms once per step,

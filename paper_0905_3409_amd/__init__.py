@@ -401,7 +401,7 @@ class Grid:
 
 class Batch:
     """Many independent 2D grids with sine stream-function fields, advanced
-    together (one persistent launch per step). ``ncells`` is a list of
+    together (one launch per step, one block per tile). ``ncells`` is a list of
     (nx, ny) cell counts; every grid is the unit square unless lo/hi are
     given per problem."""
 
