@@ -120,16 +120,19 @@ struct TileStager {
         }
     }
 
-    __device__ __forceinline__ void store(T (*tile)[S::N]) const
+    // Node f's three values sit together at tile[3 f .. 3 f + 2], so that a
+    // cell's whole stencil lies within 216 elements of its first value and
+    // every read of the gather is an immediate offset from one address.
+    __device__ __forceinline__ void store(T *tile) const
     {
         const int tid = int(threadIdx.y) * 64 + int(threadIdx.x);
 #pragma unroll
         for (int k = 0; k < S::PER; k++) {
             const int f = tid + k * kBlock;
             if (f < S::N) {
-                tile[0][f] = sv[0][k];
-                tile[1][f] = sv[1][k];
-                tile[2][f] = sv[2][k];
+                tile[3 * f] = sv[0][k];
+                tile[3 * f + 1] = sv[1][k];
+                tile[3 * f + 2] = sv[2][k];
             }
         }
     }
@@ -302,7 +305,7 @@ __device__ __forceinline__ void split_disp(const Geom &g, const int *idx, const 
         cu[a] = idx[a] + int(c[a]);
         in = in && unsigned(cu[a]) <= unsigned(g.nc[a] - 1);
     }
-    if (__all(in)) {
+    if (__builtin_expect(__all(in), 1)) {
 #pragma unroll
         for (int a = 0; a < D; a++) {
             cell[a] = cu[a];
@@ -330,20 +333,27 @@ __device__ __forceinline__ void split_disp(const Geom &g, const int *idx, const 
     }
 }
 
-// Cell data from the staged tile at index b of the cell's lower-left node:
-// every neighbour sits at a fixed offset (one row = W). The central cross
-// derivative reads one column beyond each side of the cell; at the first and
-// last cell of a row that column lies outside the grid, and the one-sided
-// differences used there do not read it (same values as gather2d).
+// Cell data from the staged tile (node-interleaved: node k's phi, psi_x,
+// psi_y at t[3 k], t[3 k + 1], t[3 k + 2]) at index b of the cell's
+// lower-left node: every neighbour sits at a fixed offset (one row = W
+// nodes). The central cross derivative reads one column beyond each side of
+// the cell; at the first and last cell of a row that column lies outside the
+// grid, and the one-sided differences used there do not read it (same
+// values as gather2d).
 template <typename T, int MIX, int W>
-__device__ __forceinline__ void gather2d_lds(const Geom &g, const T *t0, const T *t1,
-                                             const T *t2, int b, int cx, T d[4][4])
+__device__ __forceinline__ void gather2d_lds(const Geom &g, const T *tile, int b, int cx,
+                                             T d[4][4])
 {
-    d[0][0] = t0[b]; d[1][0] = t0[b + 1]; d[2][0] = t0[b + W]; d[3][0] = t0[b + W + 1];
-    d[0][1] = t1[b]; d[1][1] = t1[b + 1]; d[2][1] = t1[b + W]; d[3][1] = t1[b + W + 1];
+    // from node b - 1: offsets up to 3 (W + 2) + 2 elements, within the
+    // paired LDS reads' immediate range (255 elements) for W <= 81
+    static_assert(3 * (W + 3) + 2 <= 255, "stencil beyond the immediate offsets");
+    const T *t = tile + 3 * (b - 1);
+    auto at = [&](int k, int f) { return t[3 * (k + 1) + f]; };
+    d[0][0] = at(0, 0); d[1][0] = at(1, 0); d[2][0] = at(W, 0); d[3][0] = at(W + 1, 0);
+    d[0][1] = at(0, 1); d[1][1] = at(1, 1); d[2][1] = at(W, 1); d[3][1] = at(W + 1, 1);
     if constexpr (MIX == GALS_MIXED_CENTRAL) {
-        const T u0[4] = {t2[b - 1], t2[b], t2[b + 1], t2[b + 2]};
-        const T u1[4] = {t2[b + W - 1], t2[b + W], t2[b + W + 1], t2[b + W + 2]};
+        const T u0[4] = {at(-1, 2), at(0, 2), at(1, 2), at(2, 2)};
+        const T u1[4] = {at(W - 1, 2), at(W, 2), at(W + 1, 2), at(W + 2, 2)};
         d[0][2] = u0[1]; d[1][2] = u0[2];
         d[2][2] = u1[1]; d[3][2] = u1[2];
         const T inv2h = geo_i2h<T>(g, 0);
@@ -351,7 +361,7 @@ __device__ __forceinline__ void gather2d_lds(const Geom &g, const T *t0, const T
         diff_pair<T, sizeof(T) == 4>(u0, lo, hi, inv2h, d[0][3], d[1][3]);
         diff_pair<T, sizeof(T) == 4>(u1, lo, hi, inv2h, d[2][3], d[3][3]);
     } else {
-        d[0][2] = t2[b]; d[1][2] = t2[b + 1]; d[2][2] = t2[b + W]; d[3][2] = t2[b + W + 1];
+        d[0][2] = at(0, 2); d[1][2] = at(1, 2); d[2][2] = at(W, 2); d[3][2] = at(W + 1, 2);
         if constexpr (MIX == GALS_MIXED_CELL) {
             T ga[4], gb[4], out[4];
 #pragma unroll
@@ -380,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_step2d_affine(Geom g, TileGrid tg, A
                                                           T *__restrict__ grad_o)
 {
     using S = StageTile<4 * R>;
-    __shared__ T tile[3][S::N];
+    __shared__ T tile[3 * S::N];
     unsigned tx, ty;
     if (!xcd_tile_n(tg, tx, ty)) return;  // whole blocks only: before the barrier
     const int cx0 = int(tx) * 64 - kHaloX, ry0 = int(ty) * (4 * R) - kHaloY;
@@ -416,35 +426,45 @@ __global__ __launch_bounds__(kBlock) void k_step2d_affine(Geom g, TileGrid tg, A
         const int j = __builtin_amdgcn_readfirstlane(ry0 + kHaloY + int(threadIdx.y) + 4 * r);
         const int cx = cell[r][0], cy = cell[r][1];
         const bool on = cx - 1 >= cx0 && cx + 2 < cx0 + S::W && cy >= ry0 && cy + 1 < ry0 + S::H;
-        T d[4][4];
-        gather2d_lds<T, MIX, S::W>(g, tile[0], tile[1], tile[2],
-                                   on ? (cy - ry0) * S::W + (cx - cx0) : S::W + 1, cx, d);
-        if (!on)
+        const bool store = i < g.n[0] && j < g.n[1];
+        // the Hermite evaluation and the update from the cell data of either
+        // source; each source finishes on its own (merging the two sources'
+        // cell data before one evaluation cost register moves on every lane)
+        auto finish = [&](const T (&d)[4][4]) {
+            Basis<T> bx, by;
+            basis<T, false>(xi[r][0], geo_h<T>(g, 0), geo_ih<T>(g, 0), bx);
+            basis<T, false>(xi[r][1], geo_h<T>(g, 1), geo_ih<T>(g, 1), by);
+            T H, Hx, Hy;
+            hermite2d(d, bx, by, H, Hx, Hy);
+            if (outb[r][0]) Hx = T(0);
+            if (outb[r][1]) Hy = T(0);
+            if (!store) return;
+            const unsigned o = unsigned(j) * unsigned(g.pitch) + unsigned(i);
+            T g0, g1;
+            if constexpr (PSI == GALS_PSI_HEUN) {
+                T ps[2];
+                const T gH[2] = {Hx, Hy};
+                heun_gradient<T, 2>(am.Af, am.An, T(dt), gH, ps);
+                g0 = ps[0];
+                g1 = ps[1];
+            } else {
+                g0 = am.J[0] * Hx + am.J[2] * Hy;
+                g1 = am.J[1] * Hx + am.J[3] * Hy;
+            }
+            pstore_nt(phi_o, o, H);
+            pstore_nt(grad_o, o, g0);
+            pstore_nt(grad_o + g.plane, o, g1);
+        };
+        if (__builtin_expect(on, 1)) {
+            T d[4][4];
+            gather2d_lds<T, MIX, S::W>(g, tile, (cy - ry0) * S::W + (cx - cx0), cx, d);
+            finish(d);
+        } else {
+            T d[4][4];
             gather2d<T, MIX>(g, plane_rsrc(phi, g.plane), plane_rsrc(gx, g.plane),
                              plane_rsrc(gy, g.plane), cx, cy, d);
-        Basis<T> bx, by;
-        basis<T, false>(xi[r][0], geo_h<T>(g, 0), geo_ih<T>(g, 0), bx);
-        basis<T, false>(xi[r][1], geo_h<T>(g, 1), geo_ih<T>(g, 1), by);
-        T H, Hx, Hy;
-        hermite2d(d, bx, by, H, Hx, Hy);
-        if (outb[r][0]) Hx = T(0);
-        if (outb[r][1]) Hy = T(0);
-        if (i >= g.n[0] || j >= g.n[1]) continue;
-        const unsigned o = unsigned(j) * unsigned(g.pitch) + unsigned(i);
-        T g0, g1;
-        if constexpr (PSI == GALS_PSI_HEUN) {
-            T ps[2];
-            const T gH[2] = {Hx, Hy};
-            heun_gradient<T, 2>(am.Af, am.An, T(dt), gH, ps);
-            g0 = ps[0];
-            g1 = ps[1];
-        } else {
-            g0 = am.J[0] * Hx + am.J[2] * Hy;
-            g1 = am.J[1] * Hx + am.J[3] * Hy;
+            finish(d);
         }
-        pstore_nt(phi_o, o, H);
-        pstore_nt(grad_o, o, g0);
-        pstore_nt(grad_o + g.plane, o, g1);
     }
 }
 
