@@ -1109,6 +1109,32 @@ def bench_volume(args):
     return 0
 
 
+def device_copy_rate(nbytes=1 << 30, reps=10):
+    """What a plain device-to-device copy attains on this GPU in this run
+    (torch's copy_ of a 1 GiB FP32 tensor: the runtime's copy kernel), as
+    context for the probe's bandwidth: read + written bytes over the median
+    time of reps copies."""
+    import numpy as np
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"gbps": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes_moved": 2 * nbytes, "ms": ms,
+            "how": "torch copy_ of a 1 GiB FP32 tensor, median of 10"}
+
+
 def bench_probe(args):
     """Labelled bandwidth probe, not one of the workloads: rigid rotation (the
     cheapest velocity) on working sets far beyond the 256 MB Infinity Cache,
@@ -1166,6 +1192,9 @@ def bench_probe(args):
         torch.cuda.synchronize()
         return 0
     main = table["2d"]
+    copy = device_copy_rate()
+    log(f"plain device copy: {copy['gbps']:.0f} GB/s; the 2D probe step moves its bytes at "
+        f"{main['hbm_gbps_algorithmic'] / copy['gbps']:.2f} of that rate")
     line = {
         "metric": "bandwidth probe (not a workload): rigid rotation, FP32, 2D 8192^2 and "
                   "3D 384^3", "value": main["node_updates_per_s"], "unit": "node-updates/s",
@@ -1184,7 +1213,9 @@ def bench_probe(args):
                      "avg_launch_us": main["step_us"],
                      "alu": {"flops_per_node": PROBE_FLOPS_PER_NODE_2D,
                              "achieved_tflops": main["tflops"],
-                             "frac_of_nonpacked_fp32_peak": main["valu_frac"]}},
+                             "frac_of_nonpacked_fp32_peak": main["valu_frac"]},
+                     "device_copy": dict(copy, probe_frac_of_copy=main["hbm_gbps_algorithmic"]
+                                         / copy["gbps"])},
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
