@@ -124,7 +124,7 @@ def log(msg):
 # committed traffic record applies only while these are unchanged.
 STEP_HEADERS = ["gals_internal.h", "velocity.h", "hermite.h", "stream2d.h"]
 SINGLE_KERNEL_SOURCES = ["kernels_step.hip"] + STEP_HEADERS
-BATCH_KERNEL_SOURCES = ["batch.hip"] + STEP_HEADERS
+BATCH_KERNEL_SOURCES = ["batch.hip", "batch_shape.h", "gals_batch_api.hip"] + STEP_HEADERS
 ADJ_KERNEL_SOURCES = ["adjoint.hip", "reduce.h"] + STEP_HEADERS
 # Floating-point operations per node of the FP32 adjoint step (FMA = 2):
 # trace 346 (the forward step's jet, stages, chain and foot, 334, plus the 12

@@ -9,9 +9,12 @@
 // per-range atomic tile queues.
 // A tile is 4 waves. A wave covers WX x (64/WX) nodes with WX = 64, 32 or 16,
 // or, in the row-major shape, 64 consecutive nodes of the grid in row-major
-// order (no lanes lost to a ragged row end). Per-node arithmetic is the
+// order (no lanes lost to a ragged row end). With 64 x 1 waves, a ragged last
+// group of up to kTailPack columns is packed row-major into tiles of its
+// own (template value 1), instead of a mostly idle wave per row. Per-node arithmetic is the
 // single-grid kernel's (stream_node), so batched and single runs agree bit
 // for bit.
+#include "batch_shape.h"
 #include "stream2d.h"
 
 namespace gals {
@@ -46,6 +49,20 @@ __device__ __forceinline__ bool tile_node(const P &p, unsigned local, unsigned w
         if (ii < 0) { jj--; ii += g.n[0]; }
         else if (ii >= g.n[0]) { jj++; ii -= g.n[0]; }
         i = ii;
+        j = jj;
+        return true;
+    } else if constexpr (WX == 1u) {
+        // the packed tail strip of a 64 x 1 grid: its tail columns of every
+        // row, row-major (node k = j tail + c at column n0 - tail + c), the
+        // same division as above
+        const unsigned k = (local - body_tiles(p)) * 256u + wave * 64u + lane;
+        const int t = int(packed_tail(p));
+        if (k >= unsigned(t) * unsigned(g.n[1])) return false;
+        int jj = int(float(k) * (1.0f / float(t)));
+        int cc = int(k) - jj * t;
+        if (cc < 0) { jj--; cc += t; }
+        else if (cc >= t) { jj++; cc -= t; }
+        i = g.n[0] - t + cc;
         j = jj;
         return true;
     } else {
@@ -93,7 +110,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     if (lb >= per || t >= ntiles) return;
     const TileRef tr = tiles[t];
     const BatchProb<T> &P = probs[tr.prob];
-    if (P.wx == 64u)
+    if (P.wx == 64u && tr.local >= body_tiles(P))
+        batch_tile<T, MIX, TAYLOR, 1u>(P, tr.local, st, dt, tab, in, out);
+    else if (P.wx == 64u)
         batch_tile<T, MIX, TAYLOR, 64u>(P, tr.local, st, dt, tab, in, out);
     else if (P.wx == 32u)
         batch_tile<T, MIX, TAYLOR, 32u>(P, tr.local, st, dt, tab, in, out);
@@ -125,7 +144,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_copy(const BatchProb<T> *__res
     for (unsigned t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileRef tr = tiles[t];
         const BatchProb<T> &P = probs[tr.prob];
-        if (P.wx == 64u) copy_tile<T, 64u>(P, tr.local, in, out);
+        if (P.wx == 64u && tr.local >= body_tiles(P)) copy_tile<T, 1u>(P, tr.local, in, out);
+        else if (P.wx == 64u) copy_tile<T, 64u>(P, tr.local, in, out);
         else if (P.wx == 32u) copy_tile<T, 32u>(P, tr.local, in, out);
         else if (P.wx == 16u) copy_tile<T, 16u>(P, tr.local, in, out);
         else copy_tile<T, 0u>(P, tr.local, in, out);

@@ -14,6 +14,7 @@
 #include <new>
 #include <vector>
 
+#include "batch_shape.h"
 #include "gals_internal.h"
 
 using namespace gals;
@@ -199,6 +200,7 @@ void fill_prob(const gals_batch *b, int p, BatchProb<T> &P)
     P.wx = b->class_wx[size_class(P.g.n[0])];
     P.tiles_x = P.wx ? (unsigned(P.g.n[0]) + P.wx - 1u) / P.wx : 0u;
     P.inv_n0 = 1.0f / float(P.g.n[0]);
+    if (packed_tail(P)) P.tiles_x = unsigned(P.g.n[0]) / 64u;  // full column groups only
 }
 
 // Tiles of problem P (4 waves of 64 lanes each).
@@ -206,7 +208,9 @@ unsigned tile_count(const BatchProb<double> &P)
 {
     if (P.wx == 0u) return unsigned((P.g.nodes + 255) / 256);
     const unsigned rows = 4u * (64u / P.wx);
-    return P.tiles_x * ((unsigned(P.g.n[1]) + rows - 1u) / rows);
+    const unsigned body = P.tiles_x * ((unsigned(P.g.n[1]) + rows - 1u) / rows);
+    const uint64_t tail = uint64_t(packed_tail(P)) * uint64_t(P.g.n[1]);
+    return body + unsigned((tail + 255u) / 256u);  // body == body_tiles(P) for 64 x 1 waves
 }
 
 // Upload descriptors and the tile list (synchronous; never inside a capture).
