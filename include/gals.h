@@ -324,7 +324,10 @@ int gals_batch_set_velocity(gals_batch *b, int64_t p, int kind, const double *pa
 /* Wave shape per grid-size class (nodes per row <= 48, <= 96, <= 192, more):
  * nodes per wave along x, 64, 32 or 16 (a wave covers 64/w rows), or 0 for
  * the row-major shape (a wave takes 64 consecutive nodes of the grid in
- * row-major order). A tile is 4 waves. Default 64 for every class. */
+ * row-major order). With 64, a ragged last group of at most 48 columns is
+ * packed row-major into waves of its own. A tile is 4 waves. Default 64 for
+ * every class. The shape changes only the speed: results are the same bit
+ * for bit. */
 int gals_batch_set_tiles(gals_batch *b, const int *wave_width_per_class);
 int gals_batch_get_tiles(const gals_batch *b, int *wave_width_per_class);
 /* Advance every problem by `steps` steps (as gals_advance). use_graph != 0
