@@ -712,6 +712,7 @@ def bench_batched(args):
                 ev[1].record(s)
         s.synchronize()
 
+    torch.cuda.synchronize()  # the state was made on the current stream; steps run on s
     for _ in range(args.warmup):
         bench_step()
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -748,8 +749,10 @@ def bench_batched(args):
     # checked against FP64 single grids bit for bit in the tests)
     res = {}
     if not args.no_fp64:
-        # one advance of `inner` steps from the initial state, as timed
+        # one advance of `inner` steps from the initial state, as timed (the
+        # copy runs on the current stream and the advance on s: wait for it)
         st.copy_(ref)
+        torch.cuda.synchronize()
         bench_step()
         torch.cuda.synchronize()
         fin32 = {k: b.to_numpy(st, k) for k in range(0, len(probs), 8)}

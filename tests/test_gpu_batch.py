@@ -108,6 +108,7 @@ def test_graph_replays_equal_direct_launches(steps):
     w = _workload(sizes=SIZES[::2], seed=14)
     b, st = _batch(w, "float32", widths=(32, 32, 64, 64))
     direct = st.clone()
+    torch.cuda.synchronize()  # the clone reads st on this stream; s then writes it
     s = torch.cuda.Stream()
     for rep in range(3):
         with torch.cuda.stream(s):
@@ -128,6 +129,7 @@ def test_graph_recaptured_after_changes():
     w = _workload(sizes=SIZES[:5], seed=15)
     b, st = _batch(w, "float32")
     direct = st.clone()
+    torch.cuda.synchronize()  # the clone reads st on this stream; s then writes it
     s = torch.cuda.Stream()
     plan = [dict(t0=0.0), dict(t0=0.5), dict(t0=0.5, tiles=(16, 16, 16, 16)),
             dict(t0=0.5, vel=True)]
