@@ -55,7 +55,7 @@ __device__ __forceinline__ bool tile_node(const P &p, unsigned local, unsigned w
         // the packed tail strip of a 64 x 1 grid: its tail columns of every
         // row, row-major (node k = j tail + c at column n0 - tail + c), the
         // same division as above
-        const unsigned k = (local - body_tiles(p)) * 256u + wave * 64u + lane;
+        const unsigned k = (local & ~kTailTile) * 256u + wave * 64u + lane;
         const int t = int(packed_tail(p));
         if (k >= unsigned(t) * unsigned(g.n[1])) return false;
         int jj = int(float(k) * (1.0f / float(t)));
@@ -67,7 +67,8 @@ __device__ __forceinline__ bool tile_node(const P &p, unsigned local, unsigned w
         return true;
     } else {
         constexpr unsigned WY = 64u / WX;  // rows per wave
-        const unsigned tx = local % p.tiles_x, ty = local / p.tiles_x;
+        const unsigned sh = tile_bits(p);
+        const unsigned tx = local & ((1u << sh) - 1u), ty = local >> sh;
         i = int(tx * WX + lane % WX);
         j = int(ty * 4u * WY + wave * WY + lane / WX);
         if constexpr (WY == 1) j = __builtin_amdgcn_readfirstlane(j);
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     if (lb >= per || t >= ntiles) return;
     const TileRef tr = tiles[t];
     const BatchProb<T> &P = probs[tr.prob];
-    if (P.wx == 64u && tr.local >= body_tiles(P))
+    if (tr.local & kTailTile)
         batch_tile<T, MIX, TAYLOR, 1u>(P, tr.local, st, dt, tab, in, out);
     else if (P.wx == 64u)
         batch_tile<T, MIX, TAYLOR, 64u>(P, tr.local, st, dt, tab, in, out);
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_copy(const BatchProb<T> *__res
     for (unsigned t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileRef tr = tiles[t];
         const BatchProb<T> &P = probs[tr.prob];
-        if (P.wx == 64u && tr.local >= body_tiles(P)) copy_tile<T, 1u>(P, tr.local, in, out);
+        if (tr.local & kTailTile) copy_tile<T, 1u>(P, tr.local, in, out);
         else if (P.wx == 64u) copy_tile<T, 64u>(P, tr.local, in, out);
         else if (P.wx == 32u) copy_tile<T, 32u>(P, tr.local, in, out);
         else if (P.wx == 16u) copy_tile<T, 16u>(P, tr.local, in, out);

@@ -28,4 +28,22 @@ __host__ __device__ inline unsigned body_tiles(const P &p)
     return p.tiles_x * ((unsigned(p.g.n[1]) + 3u) / 4u);
 }
 
+// The tile index a work-list entry carries (TileRef::local). Rectangular
+// shapes: the tile's column tx in the low tile_bits bits and its row group
+// ty above them, so the kernel splits it with a mask and a shift rather than
+// a division by tiles_x. Packed tail tiles: kTailTile | their index in the
+// strip. Row-major shape: the tile's index.
+constexpr unsigned kTailTile = 0x80000000u;
+
+template <typename P>
+__host__ __device__ inline unsigned tile_bits(const P &p)
+{
+    // bits of tiles_x - 1 (0 for a single tile column)
+#ifdef __HIP_DEVICE_COMPILE__
+    return p.tiles_x > 1u ? 32u - unsigned(__clz(int(p.tiles_x - 1u))) : 0u;
+#else
+    return p.tiles_x > 1u ? 32u - unsigned(__builtin_clz(p.tiles_x - 1u)) : 0u;
+#endif
+}
+
 }  // namespace gals

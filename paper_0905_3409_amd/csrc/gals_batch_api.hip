@@ -229,7 +229,22 @@ int upload(gals_batch *b)
         const unsigned nt = tile_count(pd[p]);
         if (uint64_t(tiles.size()) + nt > (uint64_t(1) << 31))
             return bfail(GALS_EINVAL, "gals_batch: more than 2^31 tiles in one batch");
-        for (unsigned t = 0; t < nt; t++) tiles.push_back(TileRef{unsigned(p), t});
+        const BatchProb<double> &P = pd[p];
+        if (P.wx == 0u) {
+            for (unsigned t = 0; t < nt; t++) tiles.push_back(TileRef{unsigned(p), t});
+        } else {
+            // rectangular tiles row group by row group (tile_bits), then the
+            // packed tail's
+            const unsigned rows = 4u * (64u / P.wx), sh = tile_bits(P);
+            const unsigned groups = (unsigned(P.g.n[1]) + rows - 1u) / rows;
+            if ((uint64_t(groups) << sh) > uint64_t(kTailTile))
+                return bfail(GALS_EINVAL, "gals_batch: tile index of problem %d out of range", p);
+            for (unsigned ty = 0; ty < groups; ty++)
+                for (unsigned tx = 0; tx < P.tiles_x; tx++)
+                    tiles.push_back(TileRef{unsigned(p), (ty << sh) | tx});
+            for (unsigned t = P.tiles_x * groups; t < nt; t++)
+                tiles.push_back(TileRef{unsigned(p), kTailTile | (t - P.tiles_x * groups)});
+        }
     }
     hipError_t e = hipMalloc(&b->d_probs64, sizeof(BatchProb<double>) * pd.size());
     if (e == hipSuccess)
