@@ -468,6 +468,44 @@ __global__ __launch_bounds__(kBlock) void k_step2d_affine(Geom g, TileGrid tg, A
     }
 }
 
+// Node of this thread in a 3D step. Blocks are dealt to the 8 XCDs
+// round-robin by id, and each XCD has its own L2: XCD x takes the nodes of
+// every z-plane whose in-plane index (j n0 + i) lies in the x-th eighth of
+// the plane, plane after plane in blocks of kBlock. A node gathers from rows
+// j - 1 .. j + 2 of planes k and k + 1, so an XCD's gathers stay within its
+// eighth of a few planes and the next eighth's first rows, which its L2
+// holds (contiguous bands of the flat node order kept a few whole planes of
+// every field in each L2, more than it holds in 3D). Returns false past the
+// band's last node.
+__device__ __forceinline__ bool band_node3d(const Geom &g, int &i, int &j, int &k)
+{
+    const unsigned x = blockIdx.x & 7u, b = blockIdx.x >> 3;
+    const unsigned P = unsigned(g.n[0]) * unsigned(g.n[1]);  // nodes per plane
+    const unsigned s0 = unsigned((uint64_t(x) * P) >> 3);
+    const unsigned len = unsigned((uint64_t(x + 1u) * P) >> 3) - s0;  // this XCD's nodes per plane
+    const unsigned id = b * unsigned(kBlock) + threadIdx.x;
+    if (len == 0u || id >= len * unsigned(g.n[2])) return false;
+    // plane from an FP32 estimate of id / len, corrected once: id < 2^29
+    // and the quotient < 2^21, so the estimate is off by less than one
+    int kk = int(float(id) * __builtin_amdgcn_rcpf(float(len)));
+    int q = int(id) - kk * int(len);
+    if (q < 0) { kk--; q += int(len); }
+    else if (q >= int(len)) { kk++; q -= int(len); }
+    unsigned ri;
+    j = int(udiv_magic(s0 + unsigned(q), unsigned(g.n[0]), g.n_magic[0], ri));
+    i = int(ri);
+    k = kk;
+    return true;
+}
+
+// Blocks of a 3D step's launch: 8 x the blocks of the largest XCD band.
+inline unsigned band_blocks3d(const Geom &g)
+{
+    const uint64_t P = uint64_t(g.n[0]) * uint64_t(g.n[1]);
+    const uint64_t band = (P + 7u) / 8u * uint64_t(g.n[2]);
+    return unsigned(8u * ((band + kBlock - 1) / kBlock));
+}
+
 // 3D step for an affine field: the foot from the host's map, one thread per
 // node, the 64-value gather through the caches.
 template <typename T, int MIX, int PSI>
@@ -477,14 +515,8 @@ __global__ __launch_bounds__(kBlock) void k_step3d_affine(Geom g, AffineMap<T> a
                                                           T *__restrict__ phi_o,
                                                           T *__restrict__ grad_o)
 {
-    unsigned blk;
-    if (!xcd_block(unsigned((g.nodes + kBlock - 1) / kBlock), blk)) return;
-    const unsigned id = blk * kBlock + threadIdx.x;
-    if (id >= unsigned(g.nodes)) return;
-    unsigned ri, rj;
-    const unsigned row = udiv_magic(id, unsigned(g.n[0]), g.n_magic[0], ri);
-    const int k = int(udiv_magic(row, unsigned(g.n[1]), g.n_magic[1], rj));
-    const int i = int(ri), j = int(rj);
+    int i, j, k;
+    if (!band_node3d(g, i, j, k)) return;
     double sc[3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
@@ -577,14 +609,8 @@ __global__ __launch_bounds__(kBlock) void k_step3d(Geom g, Vel<T> p, Stage<T> st
                                                    const T *__restrict__ grad,
                                                    T *__restrict__ phi_o, T *__restrict__ grad_o)
 {
-    unsigned blk;
-    if (!xcd_block(unsigned((g.nodes + kBlock - 1) / kBlock), blk)) return;
-    const unsigned id = blk * kBlock + threadIdx.x;
-    if (id >= unsigned(g.nodes)) return;
-    unsigned ri, rj;
-    const unsigned row = udiv_magic(id, unsigned(g.n[0]), g.n_magic[0], ri);
-    const int k = int(udiv_magic(row, unsigned(g.n[1]), g.n_magic[1], rj));
-    const int i = int(ri), j = int(rj);
+    int i, j, k;
+    if (!band_node3d(g, i, j, k)) return;
 
     const double x[3] = {node_coord(g.lo[0], i, g.h[0]), node_coord(g.lo[1], j, g.h[1]),
                          node_coord(g.lo[2], k, g.h[2])};
@@ -686,14 +712,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 {
     constexpr bool LDS = sizeof(T) == 4;
     __shared__ T tab_s[LDS ? 24 : 1][kBlock];
-    unsigned blk;
-    if (!xcd_block(unsigned((g.nodes + kBlock - 1) / kBlock), blk)) return;
-    const unsigned id = blk * kBlock + threadIdx.x;
-    if (id >= unsigned(g.nodes)) return;
-    unsigned ri, rj;
-    const unsigned row = udiv_magic(id, unsigned(g.n[0]), g.n_magic[0], ri);
-    const int k = int(udiv_magic(row, unsigned(g.n[1]), g.n_magic[1], rj));
-    const int i = int(ri), j = int(rj);
+    int i, j, k;
+    if (!band_node3d(g, i, j, k)) return;
 
     const double x[3] = {node_coord(g.lo[0], i, g.h[0]), node_coord(g.lo[1], j, g.h[1]),
                          node_coord(g.lo[2], k, g.h[2])};
@@ -819,7 +839,7 @@ static hipError_t launch_vecpot(const gals_ctx *ctx, const Vel<T> &p, const void
                                 double c1, double c2, double c3, const void *tab, hipStream_t s)
 {
     const Stage<T> st = make_stage<T>(dt, c1, c2, c3);
-    const unsigned blocks = unsigned((ctx->g.nodes + kBlock - 1) / kBlock + 7) / 8u * 8u;
+    const unsigned blocks = band_blocks3d(ctx->g);
     hipLaunchKernelGGL((k_step3d_vecpot<T, MIX, true, PSI>), dim3(blocks),
                        dim3(kBlock), 0, s, ctx->g, p, st, dt, (const T *)tab, (const T *)phi,
                        (const T *)grad, (T *)phi_o, (T *)grad_o);
@@ -843,7 +863,8 @@ static hipError_t launch_typed(const gals_ctx *ctx, const Vel<T> &p, const void 
                                dim3(64, 4), 0, s, ctx->g, tg, am, dt, (const T *)phi,
                                (const T *)grad, (T *)phi_o, (T *)grad_o);
         } else {
-            hipLaunchKernelGGL((k_step3d_affine<T, MIX, PSI>), dim3(blocks), dim3(kBlock), 0, s,
+            hipLaunchKernelGGL((k_step3d_affine<T, MIX, PSI>), dim3(band_blocks3d(ctx->g)),
+                               dim3(kBlock), 0, s,
                                ctx->g, am, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
                                (T *)grad_o);
         }
@@ -859,7 +880,8 @@ static hipError_t launch_typed(const gals_ctx *ctx, const Vel<T> &p, const void 
         }
     } else {
         if constexpr (KIND == GALS_VEL_VECPOT_SIN || KIND == GALS_VEL_LEVEQUE3D) {
-            hipLaunchKernelGGL((k_step3d<T, KIND, MIX, PSI>), dim3(blocks), dim3(kBlock), 0, s,
+            hipLaunchKernelGGL((k_step3d<T, KIND, MIX, PSI>), dim3(band_blocks3d(ctx->g)),
+                               dim3(kBlock), 0, s,
                                ctx->g, p, st, dt, (const T *)phi, (const T *)grad, (T *)phi_o,
                                (T *)grad_o);
             return hipGetLastError();
