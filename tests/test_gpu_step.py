@@ -124,6 +124,24 @@ def test_fp64_3d_parity(name, kind, params, period, dt, steps, mixed):
     assert rel_psi(g[1], o[1], o[0], hmin) <= TOL64
 
 
+@pytest.mark.parametrize("ncell", [(2, 2, 40), (5, 3, 7), (31, 2, 9), (3, 17, 2)])
+@pytest.mark.parametrize("name,kind,params,period,dt,steps", CASES_3D[:2])
+def test_fp64_3d_parity_thin_grids(name, kind, params, period, dt, steps, ncell):
+    """Grids whose planes hold few nodes: each XCD's eighth of a plane is a
+    node or two, part of a row, or spans rows; every node still updated once
+    (the oracle at every node)."""
+    rng = np.random.default_rng(zlib.crc32((name + str(ncell)).encode()))
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    phi0, psi0 = _random_smooth_state(rng, ncell, lo, hi)
+    print(f"case 3d {name} {ncell}", flush=True)
+    g = gpu_advance(3, ncell, lo, hi, kind, params, period, phi0, psi0, 0.0, dt, steps,
+                    "float64")
+    o = oracle_advance(3, ncell, lo, hi, kind, params, period, phi0, psi0, 0.0, dt, steps)
+    hmin = min((hi[a] - lo[a]) / ncell[a] for a in range(3))
+    assert rel(g[0], o[0]) <= TOL64
+    assert rel_psi(g[1], o[1], o[0], hmin) <= TOL64
+
+
 def test_rotation_circle_full_run_fp64():
     """The 64^2 rotating circle: one revolution in 128 steps (CFL up to 2.2 at
     the corners), every node against the oracle."""
