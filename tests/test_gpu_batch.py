@@ -65,6 +65,23 @@ def test_batch_equals_single_grids_bitwise(dtype, widths):
                      f"problem {k} {p['ncell']}")
 
 
+def test_packed_tails_equal_single_grids_bitwise():
+    """64-wide waves with ragged columns packed row-major into tiles of their
+    own: tails of 1, 3, 47 and 48 columns (packed; 49 and 63 are not), a tail
+    over many rows, a grid narrower than a wave, in both precisions."""
+    import torch
+    sizes = [(2, 2000), (64, 300), (110, 90), (111, 500), (112, 40), (126, 70), (192, 33),
+             (46, 5), (200, 7)]
+    for dtype in ("float32", "float64"):
+        w = _workload(sizes=sizes, seed=18)
+        b, st = _batch(w, dtype, widths=(64, 64, 64, 64))
+        b.advance(st, 0.05, w["dt"], 3)  # odd: the copy-back kernel's tiles too
+        torch.cuda.synchronize()
+        for k, p in enumerate(w["problems"]):
+            _assert_same(b.to_numpy(st, k), _single(p, w, dtype, 0.05, 3),
+                         f"{dtype} problem {k} {p['ncell']}")
+
+
 @pytest.mark.parametrize("mixed,bc", [(pkg.MIXED_ZERO, pkg.BC_NEUMANN),
                                       (pkg.MIXED_CENTRAL, pkg.BC_EXTRAPOLATE)])
 def test_batch_modes_equal_single_grids_bitwise(mixed, bc):
