@@ -13,6 +13,9 @@ divisions run at the top of their range.
   never written;
 * the generic 2D step with v dt an integer number of cells: an exact shift of
   the data at every node, checked bit for bit on the device;
+* the same on the longest thin 3D grid (64 x 3 nodes per plane, as many
+  planes as a plane of state may hold), where the 3D kernels' estimate of a
+  node's z-plane meets its largest quotients;
 * a batch whose state spans more than 4 GiB (two of the largest grids around
   a small one): every problem bit for bit equal to the same grid advanced
   alone, for each wave shape of the tile list.
@@ -162,6 +165,42 @@ def test_integer_shift_at_the_largest_2d_grid(dtype, k, axis):
             assert torch.equal(new[:, k:], old[:, :-k])
         else:
             assert torch.equal(new[k:, :], old[:-k, :])
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+@pytest.mark.parametrize("k,axis", [(1, 2), (2, 0)])
+def test_integer_shift_on_the_longest_thin_3d_grid(dtype, k, axis):
+    """The 3D step on 64 x 3 nodes per z-plane and as many planes as a 2 GiB
+    state plane holds (2.8 M in FP32, 1.4 M in FP64). Each XCD's band of a
+    plane is then 24 nodes, so a thread finds its plane as id / 24 with id
+    up to 6.7e7 and the quotient up to 2^21.4: the largest quotients the
+    kernels' FP32 estimate of that division meets, and one correction must
+    still make it exact. v dt = k h with h, dt powers of two, so the step is
+    an exact shift of arbitrary data at every interior node."""
+    import torch
+    es = 4 if dtype == "float32" else 8
+    nz = (PLANE_LIMIT - 1) // (64 * 3 * es)  # nodes along z
+    ncell = (63, 2, nz - 1)
+    print(f"case thin 3D shift {dtype} ncell {ncell} k {k} axis {axis}", flush=True)
+    h, dt = 2.0 ** -15, 2.0 ** -14
+    hi = tuple(c * h for c in ncell)
+    F, dF = inputs.separable_sines(18, ncell, (0.0, 0.0, 0.0), hi)
+    g = pkg.Grid(ncell, (0.0, 0.0, 0.0), hi, dtype=dtype)
+    assert g.pitch == 64 and g.plane * es < PLANE_LIMIT
+    vel = np.zeros(3)
+    vel[axis] = k * h / dt
+    g.set_velocity(inputs.AFFINE, inputs.affine_params(vel, [0, 0, 0], np.zeros((3, 3))), 0.0)
+    st = _fill_state(g, F, dF)
+    ref = st.clone()
+    g.advance(st, 0.0, dt, 1)
+    torch.cuda.synchronize()
+    _whole_output_checks(g, st)
+    for a in range(4):
+        new, old = g._grid_view(st[a]), g._grid_view(ref[a])  # (z, y, x)
+        if axis == 0:
+            assert torch.equal(new[:, :, k:], old[:, :, :-k]), a
+        else:
+            assert torch.equal(new[k:], old[:-k]), a
 
 
 @pytest.mark.parametrize("dtype,widths", [("float32", (64, 64, 64, 64)),
