@@ -233,8 +233,9 @@ def main():
                     help="single workload with --profile: advance the FP64 state instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design "
-              "note, not an implemented path. Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; sharding a grid over several GPUs is "
+              "described in the design notes, not implemented. Run with --gpus 1.",
+              file=sys.stderr)
         return 2
 
     import numpy as np

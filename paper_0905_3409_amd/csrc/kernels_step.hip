@@ -485,8 +485,10 @@ __device__ __forceinline__ bool band_node3d(const Geom &g, int &i, int &j, int &
     const unsigned len = unsigned((uint64_t(x + 1u) * P) >> 3) - s0;  // this XCD's nodes per plane
     const unsigned id = b * unsigned(kBlock) + threadIdx.x;
     if (len == 0u || id >= len * unsigned(g.n[2])) return false;
-    // plane from an FP32 estimate of id / len, corrected once: id < 2^29
-    // and the quotient < 2^21, so the estimate is off by less than one
+    // plane from an FP32 estimate of id / len, corrected once: a state plane
+    // under 2 GiB keeps id < 2^27 and the quotient (a plane index) < 2^21.5,
+    // and the estimate's relative error (conversion, reciprocal, product) is
+    // under 2^-22, so it is off by less than one
     int kk = int(float(id) * __builtin_amdgcn_rcpf(float(len)));
     int q = int(id) - kk * int(len);
     if (q < 0) { kk--; q += int(len); }
